@@ -1,0 +1,280 @@
+"""Seeded synthetic inputs for lattice constrained-shortest-path instances.
+
+This module is the only code shared by the HIP path, the benchmark and the
+CPU oracle's tests.  It draws numbers and builds masks; it holds none of the
+method's arithmetic (no labels, no flows, no path sums).
+
+Lattice conventions (the paper treats subgraphs of Z^d with nearest-neighbour
+edges, section 1 and section 8):
+
+* N = n**d vertices; vertex v = sum_k c_k * n**k, axis 0 ("x") varies fastest.
+* The undirected edge u -- u+e_k has id k*N + u.  Edge arrays are SoA
+  ``[d][N]`` uint8; entry (k, u) with c_k(u) == n-1 has no edge and is 0.
+* The number of real edges is d * n**(d-1) * (n-1) (section 8 prints this
+  count for the 100^3 and 125^3 cubes).
+
+Random numbers: splitmix64 (Steele, Lea, Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014).  Output i (0-based) of the
+stream with state sigma is mix(sigma + (i+1)*gamma), which equals the i-th
+output of the sequential generator seeded with sigma.  A value in 1..K is
+1 + (((z >> 32) * K) >> 32).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+GAMMA = 0x9E3779B97F4A7C15
+_C1 = 0xBF58476D1CE4E5B9
+_C2 = 0x94D049BB133111EB
+
+
+def mix64(z: int) -> int:
+    """splitmix64 finaliser on one Python int (wraps at 2**64)."""
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * _C1) & MASK64
+    z = ((z ^ (z >> 27)) * _C2) & MASK64
+    return z ^ (z >> 31)
+
+
+def _mix64_np(z: np.ndarray) -> np.ndarray:
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(_C1)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(_C2)
+    return z ^ (z >> np.uint64(31))
+
+
+def stream(sigma: int, count: int, start: int = 0) -> np.ndarray:
+    """Outputs start .. start+count-1 of the splitmix64 stream with state sigma."""
+    i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix64_np(np.uint64(sigma & MASK64) + i * np.uint64(GAMMA))
+
+
+def stream_at(sigma: int, i: int) -> int:
+    """Output i of the stream with state sigma (scalar form of ``stream``)."""
+    return mix64((sigma + (i + 1) * GAMMA) & MASK64)
+
+
+def uniform_int(z: np.ndarray, K: int) -> np.ndarray:
+    """Map 64-bit outputs to 1..K by the multiply-high rule."""
+    return (np.uint64(1) + (((z >> np.uint64(32)) * np.uint64(K)) >> np.uint64(32)))
+
+
+def unit_double(z: int) -> float:
+    """53-bit uniform double in [0, 1) from one 64-bit output."""
+    return float(z >> 11) * (2.0 ** -53)
+
+
+# ----------------------------------------------------------------------------
+# lattice geometry helpers (pure indexing)
+# ----------------------------------------------------------------------------
+
+def num_vertices(d: int, n: int) -> int:
+    return n ** d
+
+
+def num_edges(d: int, n: int) -> int:
+    return d * n ** (d - 1) * (n - 1)
+
+
+def _grid(a: np.ndarray, d: int, n: int) -> np.ndarray:
+    """View a length-N array as numpy shape (n,)*d indexed [c_{d-1}, ..., c_0]."""
+    return a.reshape((n,) * d)
+
+
+def padding_mask(d: int, n: int) -> np.ndarray:
+    """bool [d*N]: True where entry (k, u) has no edge (c_k(u) == n-1)."""
+    N = n ** d
+    pad = np.zeros(d * N, dtype=bool)
+    for k in range(d):
+        g = _grid(pad[k * N:(k + 1) * N], d, n)
+        idx = [slice(None)] * d
+        idx[d - 1 - k] = n - 1
+        g[tuple(idx)] = True
+    return pad
+
+
+def face_mask(d: int, n: int, axis: int, coord: int) -> np.ndarray:
+    """uint8 [N]: 1 on the face c_axis == coord."""
+    m = np.zeros(n ** d, dtype=np.uint8)
+    g = _grid(m, d, n)
+    idx = [slice(None)] * d
+    idx[d - 1 - axis] = coord
+    g[tuple(idx)] = 1
+    return m
+
+
+def boundary_mask(d: int, n: int) -> np.ndarray:
+    """uint8 [N]: 1 on every vertex with some coordinate equal to 0 or n-1."""
+    m = np.zeros(n ** d, dtype=np.uint8)
+    g = _grid(m, d, n)
+    for ax in range(d):
+        for c in (0, n - 1):
+            idx = [slice(None)] * d
+            idx[ax] = c
+            g[tuple(idx)] = 1
+    return m
+
+
+def center_mask(d: int, n: int) -> np.ndarray:
+    """uint8 [N]: 1 on the single vertex with every coordinate n//2."""
+    m = np.zeros(n ** d, dtype=np.uint8)
+    v = sum((n // 2) * n ** k for k in range(d))
+    m[v] = 1
+    return m
+
+
+def vertex_index(coords, n: int) -> int:
+    """coords = (c_0, c_1, ...) -> linear index."""
+    return sum(int(c) * n ** k for k, c in enumerate(coords))
+
+
+def vertex_coords(v: int, d: int, n: int):
+    return tuple((v // n ** k) % n for k in range(d))
+
+
+# ----------------------------------------------------------------------------
+# edge arrays
+# ----------------------------------------------------------------------------
+
+def edge_stream_state(seed: int, which: int) -> int:
+    """Stream state for f1 (which=1) or f2 (which=2) of instance seed ``seed``."""
+    tag = 0xF1 if which == 1 else 0xF2
+    return mix64((seed ^ tag) & MASK64)
+
+
+def lattice_edges(d: int, n: int, seed: int, K1: int, K2: int,
+                  f1_const: int | None = None, f2_const: int | None = None,
+                  chunk: int = 1 << 23):
+    """Return (f1, f2): uint8 SoA [d*N], i.i.d. uniform on 1..K1 / 1..K2.
+
+    Entry i = k*N + v of f1 is draw i of stream edge_stream_state(seed, 1),
+    likewise f2 with state edge_stream_state(seed, 2).  A constant overrides
+    the draw.  Padding entries are 0.
+    """
+    if not (1 <= K1 <= 255 and 1 <= K2 <= 255):
+        raise ValueError("K must be in 1..255")
+    N = n ** d
+    total = d * N
+    out = []
+    for which, K, const in ((1, K1, f1_const), (2, K2, f2_const)):
+        f = np.empty(total, dtype=np.uint8)
+        if const is not None:
+            f[:] = const
+        else:
+            sigma = edge_stream_state(seed, which)
+            for s in range(0, total, chunk):
+                c = min(chunk, total - s)
+                f[s:s + c] = uniform_int(stream(sigma, c, s), K).astype(np.uint8)
+        out.append(f)
+    pad = padding_mask(d, n)
+    for f in out:
+        f[pad] = 0
+    return out[0], out[1]
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Instance:
+    d: int
+    n: int
+    f1: np.ndarray
+    f2: np.ndarray
+    A: np.ndarray
+    B: np.ndarray
+    M: int
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return self.n ** self.d
+
+
+def opposite_faces(d: int, n: int, seed: int, K1: int, K2: int, M: int,
+                   name: str = "", f1_const=None, f2_const=None) -> Instance:
+    f1, f2 = lattice_edges(d, n, seed, K1, K2, f1_const, f2_const)
+    return Instance(d, n, f1, f2, face_mask(d, n, 0, 0), face_mask(d, n, 0, n - 1), M,
+                    name=name, meta=dict(seed=seed, K1=K1, K2=K2))
+
+
+def square64(seed: int = 1, M: int = 200) -> Instance:
+    """2-D 64x64, f1,f2 uniform 1..5, A = column x=0, B = column x=63."""
+    return opposite_faces(2, 64, seed, 5, 5, M, name=f"square64_s{seed}_M{M}")
+
+
+def cube128(seed: int = 11, M: int = 700) -> Instance:
+    """3-D 128^3, f1,f2 uniform 1..10, A = face x=0, B = face x=127."""
+    return opposite_faces(3, 128, seed, 10, 10, M, name=f"cube128_s{seed}_M{M}")
+
+
+def cube256(seed: int = 21, M: int = 10000) -> Instance:
+    """3-D 256^3, f1,f2 uniform 1..100 (long edge timers), faces x=0 / x=255."""
+    return opposite_faces(3, 256, seed, 100, 100, M, name=f"cube256_s{seed}_M{M}")
+
+
+def cube256_stress(seed: int = 22, M: int = 10000) -> Instance:
+    """3-D 256^3, f1 == 1, f2 uniform 1..3 (thick, BFS-like frontier)."""
+    return opposite_faces(3, 256, seed, 1, 3, M, name=f"cube256stress_s{seed}_M{M}",
+                          f1_const=1)
+
+
+def cube_boundary_to_center(n: int, seed: int, K: int = 100, M: int = 10000) -> Instance:
+    """3-D n^3 with water on the cube boundary and B the centre (section 8's runs)."""
+    f1, f2 = lattice_edges(3, n, seed, K, K)
+    return Instance(3, n, f1, f2, boundary_mask(3, n), center_mask(3, n), M,
+                    name=f"cube{n}_boundary_s{seed}", meta=dict(seed=seed, K1=K, K2=K))
+
+
+def _round_half_up(x: float) -> int:
+    return int(math.floor(x + 0.5))
+
+
+def mixed_params(master: int, j: int, lo2=(32, 512), lo3=(16, 160)):
+    """Parameters (seed, d, n, K, M) of instance j of a mixed batch.
+
+    s_j is output j of the stream with state ``master``; outputs g0..g3 of the
+    stream with state s_j give d, n (log-uniform), K (3..50) and
+    M = round((1.5 + 2.5 u') * n * (K+1) / 2).
+    """
+    s = stream_at(master, j)
+    g0, g1, g2, g3 = (stream_at(s, i) for i in range(4))
+    d = 2 + (g0 >> 63)
+    lo, hi = lo2 if d == 2 else lo3
+    u = unit_double(g1)
+    n = _round_half_up(lo * (hi / lo) ** u)
+    K = 3 + (((g2 >> 32) * 48) >> 32)
+    u2 = unit_double(g3)
+    M = _round_half_up((1.5 + 2.5 * u2) * n * (K + 1) / 2)
+    return s, int(d), int(n), int(K), int(M)
+
+
+def mixed_instance(master: int, j: int, lo2=(32, 512), lo3=(16, 160)) -> Instance:
+    s, d, n, K, M = mixed_params(master, j, lo2, lo3)
+    inst = opposite_faces(d, n, s, K, K, M, name=f"mixed{master}_{j}")
+    inst.meta.update(K=K, j=j)
+    return inst
+
+
+def batch_params(count: int = 1024, master: int = 41):
+    """Mixed batch: d in {2,3}, n log-uniform in [32,512] (2-D) / [16,160] (3-D)."""
+    return [mixed_params(master, j) for j in range(count)]
+
+
+def serving_params(count: int, master: int = 51):
+    """Serving mix: sides log-uniform 64..1024 (2-D) and 32..256 (3-D)."""
+    return [mixed_params(master, j, (64, 1024), (32, 256)) for j in range(count)]
+
+
+def poisson_arrivals(count: int, qps: float, seed: int = 52) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream: exponential gaps from stream ``seed``."""
+    z = stream(mix64(seed), count)
+    u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    gaps = -np.log1p(-u) / qps
+    return np.cumsum(gaps)

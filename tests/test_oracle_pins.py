@@ -1,0 +1,347 @@
+"""Pin the CPU oracle to things other than itself (no GPU needed).
+
+Each test compares the oracle against a computation that shares no code with
+it: exhaustive simple paths, Dijkstra over (vertex, quality) states, the
+time-indexed recurrence (which also fixes every counter), textbook Dijkstra
+in the unconstrained and infeasible limits, closed forms, and numbers the
+paper prints (section 3's worked example, section 8's edge counts).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1511_06441_amd import inputs as gen
+from tests import pins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _inst(d, n, seed, K1, K2, M, f1c=None, f2c=None):
+    return gen.opposite_faces(d, n, seed, K1, K2, M, f1_const=f1c, f2_const=f2c)
+
+
+def _check_tuple(r, T, X, x, Y, F2):
+    assert (r.T, r.X, r.x, r.Y, r.F2) == (T, X, x, Y, F2)
+
+
+# ---------------------------------------------------------------------------
+# generator and lattice geometry
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_published_first_output():
+    # splitmix64 seeded with 0 first returns 0xE220A8397B1DCDAF
+    assert gen.mix64(gen.GAMMA) == 0xE220A8397B1DCDAF
+    assert int(gen.stream(0, 1)[0]) == 0xE220A8397B1DCDAF
+
+
+def test_stream_is_sequential_generator():
+    sigma = 12345
+    z = gen.stream(sigma, 5)
+    state = sigma
+    for i in range(5):
+        state = (state + gen.GAMMA) & gen.MASK64
+        assert int(z[i]) == gen.mix64(state)
+    assert int(gen.stream(sigma, 2, 3)[1]) == int(z[4])
+
+
+def test_uniform_range_and_mean():
+    v = gen.uniform_int(gen.stream(7, 200000), 10)
+    assert v.min() == 1 and v.max() == 10
+    assert abs(v.astype(float).mean() - 5.5) < 0.03
+
+
+@pytest.mark.parametrize("n,edges", [(100, 2_970_000), (125, 5_812_500)])
+def test_edge_count_printed_in_paper(n, edges):
+    # section 8 prints the edge counts of the 100^3 and 125^3 cubes
+    assert gen.num_edges(3, n) == edges
+    pad = gen.padding_mask(3, n)
+    assert int((~pad).sum()) == edges
+
+
+def test_oracle_adjacency_counts_and_order():
+    d, n = 3, 20
+    f1, f2 = gen.lattice_edges(d, n, 3, 9, 9)
+    off, nbr, a1, a2, eid = O.lattice_adjacency(d, n, f1, f2)
+    assert off[-1] == 2 * gen.num_edges(d, n)
+    # neighbours listed ascending, and each entry's times are the edge's
+    N = n ** d
+    for v in (0, 1, 399, 4210, N - 1):
+        row = nbr[off[v]:off[v + 1]]
+        assert list(row) == sorted(row)
+        for j in range(off[v], off[v + 1]):
+            u, w = min(v, nbr[j]), max(v, nbr[j])
+            k = int(np.log(w - u) / np.log(n) + 1e-9)
+            assert eid[j] == k * N + u
+            assert a1[j] == f1[k * N + u] and a2[j] == f2[k * N + u]
+
+
+# ---------------------------------------------------------------------------
+# P1: exhaustive simple paths on the smallest lattices
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n", [(2, 2), (2, 3), (3, 2), (1, 5)])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_oracle_vs_all_simple_paths(d, n, seed):
+    f1, f2 = gen.lattice_edges(d, n, seed, 4, 4)
+    A, B = gen.face_mask(d, n, 0, 0), gen.face_mask(d, n, 0, n - 1)
+    edges = pins.lattice_edge_list(d, n, f1, f2)
+    Mmax = int(edges[3].sum()) + 2
+    for M in range(1, Mmax + 1):
+        T, X, x, Y, F2, lab = pins.paths_solve(n ** d, edges, A, B, M)
+        r = O.solve(d, n, f1, f2, A, B, M)
+        _check_tuple(r, T, X, x, Y, F2)
+        assert np.array_equal(r.labels.astype(np.int64), lab), M
+
+
+# ---------------------------------------------------------------------------
+# P2: Dijkstra over (vertex, quality) states
+# ---------------------------------------------------------------------------
+
+STATE_CASES = [
+    # d, n, seed, K1, K2, M
+    (1, 30, 5, 6, 6, 60),
+    (2, 6, 1, 5, 5, 25),
+    (2, 8, 2, 5, 5, 30),
+    (2, 8, 3, 9, 3, 12),
+    (2, 10, 4, 3, 7, 45),
+    (3, 4, 5, 5, 5, 22),
+    (3, 5, 6, 10, 10, 40),
+    (2, 7, 7, 255, 255, 900),
+    (4, 3, 8, 4, 4, 20),
+]
+
+
+@pytest.mark.parametrize("case", STATE_CASES)
+def test_oracle_vs_state_dijkstra(case):
+    d, n, seed, K1, K2, M = case
+    inst = _inst(d, n, seed, K1, K2, M)
+    edges = pins.lattice_edge_list(d, n, inst.f1, inst.f2)
+    T, X, x, Y, F2, lab, imp = pins.states_solve(inst.N, edges, inst.A, inst.B, M)
+    r = O.solve_instance(inst)
+    _check_tuple(r, T, X, x, Y, F2)
+    assert np.array_equal(r.labels.astype(np.int64), lab)
+    # U counts every (vertex, time) at which a label rose, A once at time 0
+    assert r.counters["U"] == int(imp.sum())
+
+
+def test_state_dijkstra_sweeps_M():
+    d, n = 2, 7
+    f1, f2 = gen.lattice_edges(d, n, 9, 6, 6)
+    A, B = gen.face_mask(d, n, 0, 0), gen.face_mask(d, n, 0, n - 1)
+    edges = pins.lattice_edge_list(d, n, f1, f2)
+    prevT = None
+    for M in range(1, 60):
+        T, X, x, Y, F2, lab, imp = pins.states_solve(n * n, edges, A, B, M)
+        r = O.solve(d, n, f1, f2, A, B, M)
+        _check_tuple(r, T, X, x, Y, F2)
+        assert np.array_equal(r.labels.astype(np.int64), lab)
+        # P8: a looser constraint never makes the answer later
+        if prevT is not None and prevT >= 0:
+            assert 0 <= r.T <= prevT
+        prevT = r.T
+
+
+# ---------------------------------------------------------------------------
+# P3: the time-indexed recurrence fixes labels and every counter
+# ---------------------------------------------------------------------------
+
+DP_CASES = [
+    (2, 12, 1, 5, 5, 50),
+    (2, 16, 2, 3, 8, 70),
+    (3, 6, 3, 10, 10, 60),
+    (3, 7, 4, 2, 2, 12),
+    (1, 40, 5, 7, 7, 100),
+    (2, 9, 6, 5, 5, 8),        # infeasible: runs until nothing is in transit
+]
+
+
+@pytest.mark.parametrize("case", DP_CASES)
+def test_oracle_vs_recurrence_with_counters(case):
+    d, n, seed, K1, K2, M = case
+    inst = _inst(d, n, seed, K1, K2, M)
+    edges = pins.lattice_edge_list(d, n, inst.f1, inst.f2)
+    ref = pins.dp_solve(inst.N, edges, inst.A, inst.B, M)
+    r = O.solve_instance(inst)
+    _check_tuple(r, ref["T"], ref["X"], ref["x"], ref["Y"], ref["F2"])
+    assert np.array_equal(r.labels.astype(np.int64), ref["labels"])
+    assert r.counters == ref["counters"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_square64_vs_recurrence(seed):
+    inst = gen.square64(seed)
+    edges = pins.lattice_edge_list(inst.d, inst.n, inst.f1, inst.f2)
+    ref = pins.dp_solve(inst.N, edges, inst.A, inst.B, inst.M)
+    r = O.solve_instance(inst)
+    _check_tuple(r, ref["T"], ref["X"], ref["x"], ref["Y"], ref["F2"])
+    assert np.array_equal(r.labels.astype(np.int64), ref["labels"])
+    assert r.counters == ref["counters"]
+
+
+# ---------------------------------------------------------------------------
+# P4 / P5: textbook Dijkstra in the two limits of M
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n,seed,K", [(2, 64, 1, 5), (3, 20, 2, 10), (2, 40, 3, 100)])
+def test_unconstrained_limit_is_dijkstra_on_f1(d, n, seed, K):
+    f1, f2 = gen.lattice_edges(d, n, seed, K, K)
+    A, B = gen.face_mask(d, n, 0, 0), gen.face_mask(d, n, 0, n - 1)
+    edges = pins.lattice_edge_list(d, n, f1, f2)
+    M = int(edges[3].sum()) + 1
+    T, X, F2 = pins.scipy_unconstrained(n ** d, edges, A, B)
+    r = O.solve(d, n, f1, f2, A, B, M, want_labels=False)
+    assert (r.T, r.X, r.F2) == (T, X, F2)
+
+
+@pytest.mark.parametrize("d,n,seed,K", [(2, 64, 1, 5), (3, 16, 2, 10)])
+def test_infeasible_limit_labels_are_dijkstra_on_f2(d, n, seed, K):
+    f1, f2 = gen.lattice_edges(d, n, seed, K, K)
+    A, B = gen.face_mask(d, n, 0, 0), gen.face_mask(d, n, 0, n - 1)
+    edges = pins.lattice_edge_list(d, n, f1, f2)
+    lab0, dist = pins.scipy_infeasible_labels(n ** d, edges, A, 1)
+    dAB = int(dist[B.astype(bool)].min())
+    for M in (dAB, dAB - 1, max(dAB // 2, 1)):
+        r = O.solve(d, n, f1, f2, A, B, M)
+        _check_tuple(r, -1, -1, -1, -1, -1)
+        lab, _ = pins.scipy_infeasible_labels(n ** d, edges, A, M)
+        assert np.array_equal(r.labels.astype(np.int64), lab)
+    # one more unit of budget and B is reachable
+    r = O.solve(d, n, f1, f2, A, B, dAB + 1, want_labels=False)
+    assert r.T > 0 and r.F2 == dAB
+
+
+# ---------------------------------------------------------------------------
+# P6 / P7: closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n,seed", [(2, 32, 22), (3, 16, 22), (3, 24, 5)])
+def test_unit_times_closed_form(d, n, seed):
+    inst = _inst(d, n, seed, 1, 3, 10000, f1c=1)
+    r = O.solve_instance(inst, want_labels=False)
+    _check_tuple(r, *pins.straight_line_answer(d, n, inst.f2))
+
+
+@pytest.mark.parametrize("d,n", [(1, 9), (2, 13), (3, 8)])
+def test_all_ones_closed_form(d, n):
+    for M in (n - 1, n, n + 5):
+        inst = _inst(d, n, 1, 1, 1, M, f1c=1, f2c=1)
+        r = O.solve_instance(inst, want_labels=False)
+        if M >= n:
+            assert r.T == n - 1 and r.F2 == n - 1 and r.X == n - 1
+            assert r.Y == n - 2 and r.x == n - 2
+        else:
+            _check_tuple(r, -1, -1, -1, -1, -1)
+
+
+# ---------------------------------------------------------------------------
+# P8: invariants and path recovery
+# ---------------------------------------------------------------------------
+
+def test_labels_never_decrease_over_cycles():
+    inst = _inst(2, 14, 4, 6, 6, 60)
+    full = O.solve_instance(inst, trace_cap=10000)
+    prev = None
+    for k in range(1, full.counters["C"] + 1):
+        r = O.solve_instance(inst, max_cycles=k)
+        lab = r.labels.astype(np.int64)
+        assert lab.min() >= 0 and lab.max() <= inst.M
+        assert np.all(lab[inst.A.astype(bool)] == inst.M)
+        if prev is not None:
+            assert np.all(lab >= prev)
+        prev = lab
+    assert np.array_equal(prev, full.labels.astype(np.int64))
+    # trace: strictly increasing times, one row per cycle
+    t = full.trace[:, 0]
+    assert len(t) == full.counters["C"] and np.all(np.diff(t) > 0) and t[-1] == full.T
+    assert full.trace[:, 1].sum() == full.counters["R"]
+    assert full.trace[:, 3].sum() + 0 <= full.counters["E"]
+
+
+@pytest.mark.parametrize("case", [(2, 12, 1, 5, 5, 50), (3, 6, 3, 10, 10, 60), (2, 64, 2, 5, 5, 200)])
+def test_reconstruction_is_an_optimal_path(case):
+    d, n, seed, K1, K2, M = case
+    inst = _inst(d, n, seed, K1, K2, M)
+    path, res, steps = O.reconstruct(d, n, inst.f1, inst.f2, inst.A, inst.B, M)
+    N = inst.N
+    assert inst.A[path[0]] == 1 and path[-1] == res.X and inst.B[res.X] == 1
+    assert len(set(path.tolist())) == len(path)              # simple
+    F1 = F2 = 0
+    for u, v in zip(path[:-1], path[1:]):
+        lo, hi = min(u, v), max(u, v)
+        k = [k for k in range(d) if hi - lo == n ** k]
+        assert len(k) == 1
+        k = k[0]
+        assert (lo // n ** k) % n < n - 1                    # a lattice edge
+        F1 += int(inst.f1[k * N + lo])
+        F2 += int(inst.f2[k * N + lo])
+    assert (F1, F2) == (res.T, res.F2) and F2 < M
+    # each re-solve ends one edge earlier: T' = T - f1(x), F2' = F2 - f2(x)
+    for a, b in zip(steps[:-1], steps[1:]):
+        x = int(a[2])
+        assert b[0] == a[0] - inst.f1[x] and b[4] == a[4] - inst.f2[x] and b[1] == a[3]
+
+
+def test_empty_A_and_invalid_inputs():
+    inst = _inst(2, 6, 1, 5, 5, 30)
+    r = O.solve(2, 6, inst.f1, inst.f2, np.zeros(36, np.uint8), inst.B, 30)
+    _check_tuple(r, -1, -1, -1, -1, -1)
+    assert r.labels.max() == 0
+    with pytest.raises(O.OracleError):
+        O.solve(2, 6, inst.f1, inst.f2, inst.A, inst.A, 30)   # A and B overlap
+    bad = inst.f1.copy()
+    bad[0] = 0
+    with pytest.raises(O.OracleError):
+        O.solve(2, 6, bad, inst.f2, inst.A, inst.B, 30)       # zero passage time
+    with pytest.raises(O.OracleError):
+        O.solve(2, 6, inst.f1, inst.f2, inst.A, inst.B, 0)    # M must be positive
+
+
+# ---------------------------------------------------------------------------
+# section 3: the worked example's printed numbers
+# ---------------------------------------------------------------------------
+
+def _worked_example():
+    with open(os.path.join(GOLDEN, "worked_example.json")) as fh:
+        ex = json.load(fh)
+    nv = ex["vertices"] + 1                                     # vertex 0 unused
+    graph = O.graph_from_edges(nv, [tuple(e) for e in ex["edges"]])
+    A = np.zeros(nv, np.uint8)
+    A[ex["A"]] = 1
+    B = np.zeros(nv, np.uint8)
+    B[ex["B"]] = 1
+    return ex, graph, A, B
+
+
+def test_worked_example_printed_values():
+    ex, graph, A, B = _worked_example()
+    M = ex["M"]
+    full = O.solve_graph(graph, A, B, M, trace_cap=100)
+    assert full.T == ex["T"] and full.F2 == ex["F2"] and full.X == ex["B"][0]
+    times = full.trace[:, 0].tolist()
+    for ev in ex["label_events"]:
+        v, t, before, after = ev["vertex"], ev["time"], ev["before"], ev["after"]
+        k = times.index(t) + 1                                  # cycles up to time t
+        at = O.solve_graph(graph, A, B, M, max_cycles=k).labels
+        pre = O.solve_graph(graph, A, B, M, max_cycles=k - 1).labels
+        assert (int(pre[v]), int(at[v])) == (before, after), ev
+    # the printed minimising path is optimal: its sums are (T, F2)
+    w = {(min(u, v), max(u, v)): (a, b) for u, v, a, b in ex["edges"]}
+    p = ex["printed_path"]
+    sums = np.sum([w[(min(u, v), max(u, v))] for u, v in zip(p[:-1], p[1:])], axis=0)
+    assert tuple(int(s) for s in sums) == (ex["T"], ex["F2"])
+    # repeated solves recover an optimal path (ties go to the smaller vertex)
+    path, res, _ = O.reconstruct_graph(graph, A, B, M)
+    assert path.tolist() == ex["recovered_path"]
+
+
+def test_worked_example_vs_state_dijkstra():
+    ex, graph, A, B = _worked_example()
+    nv = ex["vertices"] + 1
+    edges = pins.edges_from_list([tuple(e) for e in ex["edges"]])
+    T, X, x, Y, F2, lab, imp = pins.states_solve(nv, edges, A, B, ex["M"])
+    r = O.solve_graph(graph, A, B, ex["M"])
+    _check_tuple(r, T, X, x, Y, F2)
+    assert np.array_equal(r.labels.astype(np.int64), lab)
