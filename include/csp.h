@@ -1,0 +1,137 @@
+/*
+ * csp.h -- C ABI of libcsp, an MI355X (gfx950) solver for the constrained
+ * shortest path problem on lattice cubes in Z^d by the water-flow,
+ * label-correcting method of I. Matic, "A parallel algorithm for the
+ * constrained shortest path problem on lattice graphs" (arXiv:1511.06441).
+ *
+ * Problem (section 1 of the paper): every edge e of the nearest-neighbour
+ * lattice on n^d vertices carries a passage time f1(e) and a weight f2(e),
+ * both positive integers.  For disjoint vertex sets A and B and a budget M,
+ * find the least total time F1 of a path from A to B whose total weight
+ * satisfies F2 < M.
+ *
+ * Method (sections 1, 4-6, Algorithms 1-11): water of quality M starts on A;
+ * crossing e takes f1(e) time units and costs f2(e) quality; water of quality
+ * 0 stops.  Label(P) is the best quality that has reached P.  Time advances
+ * to the next delivery; vertices whose label improves send water on to every
+ * neighbour they would improve.  The answer is the first time a vertex of B
+ * receives water (section 5, "Termination").
+ *
+ * Conventions shared by every entry point:
+ *   N = n^d.  Vertex v = sum_k c_k n^k (axis 0 varies fastest).
+ *   Edge arrays f1, f2: uint8, SoA [d][N]; entry (k, u) is the edge joining
+ *     u and u + n^k, id k*N + u.  Entries with c_k(u) = n-1 have no edge and
+ *     are ignored.  Real edges need 1 <= f1, f2 <= 255.
+ *   Masks A, B: uint8 [N], nonzero = member.  A and B must be disjoint.
+ *   M: 1 <= M <= CSP_MAX_M.  The constraint is strict (F2 < M).
+ *   Labels (optional output): uint32 [N], the best quality at each vertex at
+ *     the answer time T (at the end of the run when there is no path).
+ *
+ * Result (section 1, section 5 "Termination"):
+ *   T  least F1 (time of the first delivery to B)
+ *   X  the vertex of B reached at T with the largest label, smallest index
+ *      on ties
+ *   x  id of the last edge (Y, X) of an optimal path: the delivery to X at T
+ *      carrying its label, from the smallest such Y
+ *   Y  the other end of x (the vertex before X)
+ *   F2 M - Label(X), the total weight of that path
+ *   No path is not an error: CSP_OK with T = X = x = Y = F2 = -1.
+ *
+ * Counters (optional output): C cycles (distinct delivery times), U label
+ * improvements (A counted once at time 0), D neighbour tests, E flows sent,
+ * R flows delivered, P peak flows in transit after a sending round, I
+ * largest improved set of one cycle.
+ *
+ * Errors: every entry point returns CSP_OK or a negative code and leaves
+ * outputs unspecified on error.  The library never frees caller memory.
+ * A context is used by one host thread at a time.
+ */
+#ifndef CSP_H
+#define CSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSP_MAX_M 0x0FFFFFFFu
+
+enum {
+    CSP_OK = 0,
+    CSP_EINVAL = -1,     /* bad size, mask, edge value or M */
+    CSP_ENOMEM = -2,     /* device allocation failed */
+    CSP_EDEVICE = -3,    /* a HIP call failed */
+    CSP_EOVERFLOW = -4,  /* transit pool still too small after retries */
+    CSP_ECANCELED = -5   /* cycle cap reached before the run ended */
+};
+
+typedef struct { int64_t T, X, x, Y, F2; } csp_result;
+typedef struct { int64_t C, U, D, E, R, P, I; } csp_counters;
+
+typedef struct csp_ctx csp_ctx;
+
+/* Create a context on HIP device `device`.  The context owns its device
+ * scratch (labels, frontier queues, the transit pool) and grows it on
+ * demand; it owns no caller buffer. */
+int csp_create(int device, csp_ctx **out);
+void csp_destroy(csp_ctx *ctx);
+
+/* Error text of the last failing call on ctx (static storage). */
+const char *csp_last_error(const csp_ctx *ctx);
+
+/* One solve (sections 4-6, Algorithm 1) on device-resident inputs.
+ * f1, f2, A, B are device pointers laid out as above; labels (nullable) is
+ * a device uint32 [N] output.  Work is enqueued on `stream` (a hipStream_t,
+ * NULL = default stream); the call returns after the result has been copied
+ * back, so *out (and *cnt, nullable) are valid on return.
+ * max_cycles <= 0 means no cap; otherwise CSP_ECANCELED when it is hit. */
+int csp_solve_dev(csp_ctx *ctx, int d, int64_t n,
+                  const uint8_t *f1, const uint8_t *f2,
+                  const uint8_t *A, const uint8_t *B, uint32_t M,
+                  uint32_t *labels, csp_result *out, csp_counters *cnt,
+                  int64_t max_cycles, void *stream);
+
+/* Same on host buffers: copies inputs to the device of ctx, solves, copies
+ * labels (nullable host uint32 [N]) back.  Synchronous. */
+int csp_solve(csp_ctx *ctx, int d, int64_t n,
+              const uint8_t *f1, const uint8_t *f2,
+              const uint8_t *A, const uint8_t *B, uint32_t M,
+              uint32_t *labels, csp_result *out, csp_counters *cnt);
+
+/* Path recovery by repeated solves (section 1; section 5, "Termination"):
+ * after (T, X, x = (Y, X), F2), solve again with the same A, B' = {Y} and
+ * M' = F2 - f2(x) + 1; that solve ends at Y at time T - f1(x) with weight
+ * F2 - f2(x) and names the vertex before Y.  Repeat until it is in A.
+ * path (host int64 [cap]) receives the vertices from the A end to X and
+ * *len their number; CSP_EINVAL with *len set when cap is too small.  No
+ * path gives *len = 0.  Inputs are device pointers as for csp_solve_dev.
+ * `scratch_mask` is a caller-owned device uint8 [N] used for B'; it must be
+ * all zero on entry and is all zero again on return. */
+int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n,
+                        const uint8_t *f1, const uint8_t *f2,
+                        const uint8_t *A, const uint8_t *B, uint32_t M,
+                        uint8_t *scratch_mask,
+                        int64_t *path, int64_t cap, int64_t *len,
+                        csp_result *out, void *stream);
+
+/* Device time (ms, from HIP events on the solve stream) of the cycle kernel
+ * of the last successful csp_solve_dev on ctx; excludes input checks and
+ * result copies. */
+int csp_last_kernel_ms(const csp_ctx *ctx, float *ms);
+
+/* Starting capacity of each timing-wheel bucket, in flows (0 = automatic).
+ * A run that overflows a bucket is repeated with twice the capacity, so
+ * this changes speed and memory, never results. */
+int csp_set_pool_hint(csp_ctx *ctx, uint64_t flows_per_bucket);
+
+/* Workgroups of the cycle kernel for later solves on ctx (0 = automatic;
+ * clamped to what the device can keep resident at once).  Changes speed,
+ * never results. */
+int csp_set_blocks(csp_ctx *ctx, int blocks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSP_H */

@@ -1,0 +1,217 @@
+"""Thin ctypes binding of libcsp (include/csp.h).  Argument marshalling only:
+every step of a solve runs in the HIP library.  PyTorch supplies device
+memory and streams.
+
+Importing this module loads ``libcsp.so`` from this package directory and
+raises if it is missing; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsp.so")
+
+CSP_OK = 0
+CSP_EINVAL = -1
+CSP_ENOMEM = -2
+CSP_EDEVICE = -3
+CSP_EOVERFLOW = -4
+CSP_ECANCELED = -5
+CSP_MAX_M = 0x0FFFFFFF
+
+EXPORTED = (
+    "csp_create", "csp_destroy", "csp_last_error", "csp_solve_dev", "csp_solve",
+    "csp_reconstruct_dev", "csp_last_kernel_ms", "csp_set_pool_hint",
+    "csp_set_blocks",
+)
+
+
+class csp_result(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int64), ("X", ctypes.c_int64), ("x", ctypes.c_int64),
+                ("Y", ctypes.c_int64), ("F2", ctypes.c_int64)]
+
+    def tuple(self):
+        return (self.T, self.X, self.x, self.Y, self.F2)
+
+
+class csp_counters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("C", "U", "D", "E", "R", "P", "I")]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcsp.so not built ({LIB_PATH}); run python -m paper_1511_06441_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i64, u32, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int
+    lib.csp_create.argtypes = [i32, ctypes.POINTER(p)]
+    lib.csp_create.restype = i32
+    lib.csp_destroy.argtypes = [p]
+    lib.csp_destroy.restype = None
+    lib.csp_last_error.argtypes = [p]
+    lib.csp_last_error.restype = ctypes.c_char_p
+    lib.csp_solve_dev.argtypes = [p, i32, i64, p, p, p, p, u32, p, ctypes.POINTER(csp_result),
+                                  ctypes.POINTER(csp_counters), i64, p]
+    lib.csp_solve_dev.restype = i32
+    lib.csp_solve.argtypes = [p, i32, i64, p, p, p, p, u32, p, ctypes.POINTER(csp_result),
+                              ctypes.POINTER(csp_counters)]
+    lib.csp_solve.restype = i32
+    lib.csp_reconstruct_dev.argtypes = [p, i32, i64, p, p, p, p, u32, p, p, i64,
+                                        ctypes.POINTER(i64), ctypes.POINTER(csp_result), p]
+    lib.csp_reconstruct_dev.restype = i32
+    lib.csp_last_kernel_ms.argtypes = [p, ctypes.POINTER(ctypes.c_float)]
+    lib.csp_last_kernel_ms.restype = i32
+    lib.csp_set_pool_hint.argtypes = [p, ctypes.c_uint64]
+    lib.csp_set_pool_hint.restype = i32
+    lib.csp_set_blocks.argtypes = [p, i32]
+    lib.csp_set_blocks.restype = i32
+    return lib
+
+
+lib = _load()
+
+
+class CspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcsp error {code}: {msg}")
+        self.code = code
+
+
+def _check(ctx, rc):
+    if rc != CSP_OK:
+        msg = lib.csp_last_error(ctx).decode() if ctx else ""
+        raise CspError(rc, msg)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# --- the C entry points, same names ---------------------------------------
+
+def csp_create(device: int = 0):
+    h = ctypes.c_void_p()
+    _check(None, lib.csp_create(device, ctypes.byref(h)))
+    return h
+
+
+def csp_destroy(ctx):
+    lib.csp_destroy(ctx)
+
+
+def csp_last_error(ctx) -> str:
+    return lib.csp_last_error(ctx).decode()
+
+
+def csp_solve_dev(ctx, d, n, f1, f2, A, B, M, labels=None, counters=True, max_cycles=0,
+                  stream=None):
+    """Device tensors (uint8 f1/f2 [d*N], A/B [N]; int32/uint32 labels [N])."""
+    res = csp_result()
+    cnt = csp_counters()
+    rc = lib.csp_solve_dev(ctx, d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), M, _ptr(labels),
+                           ctypes.byref(res), ctypes.byref(cnt) if counters else None,
+                           max_cycles, _stream(stream))
+    _check(ctx, rc)
+    return res, (cnt if counters else None)
+
+
+def csp_solve(ctx, d, n, f1, f2, A, B, M, labels=None):
+    """Host numpy arrays; labels (numpy uint32 [N]) is filled if given."""
+    res = csp_result()
+    cnt = csp_counters()
+    addr = lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None
+    rc = lib.csp_solve(ctx, d, n, addr(f1), addr(f2), addr(A), addr(B), M, addr(labels),
+                       ctypes.byref(res), ctypes.byref(cnt))
+    _check(ctx, rc)
+    return res, cnt
+
+
+def csp_reconstruct_dev(ctx, d, n, f1, f2, A, B, M, scratch_mask, cap, stream=None):
+    import numpy as np
+    path = np.zeros(max(cap, 1), dtype=np.int64)
+    ln = ctypes.c_int64()
+    res = csp_result()
+    rc = lib.csp_reconstruct_dev(ctx, d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), M,
+                                 _ptr(scratch_mask), ctypes.c_void_p(path.ctypes.data), cap,
+                                 ctypes.byref(ln), ctypes.byref(res), _stream(stream))
+    _check(ctx, rc)
+    return path[:ln.value].copy(), res
+
+
+def csp_last_kernel_ms(ctx) -> float:
+    ms = ctypes.c_float()
+    _check(ctx, lib.csp_last_kernel_ms(ctx, ctypes.byref(ms)))
+    return ms.value
+
+
+def csp_set_pool_hint(ctx, flows_per_bucket: int):
+    _check(ctx, lib.csp_set_pool_hint(ctx, flows_per_bucket))
+
+
+def csp_set_blocks(ctx, blocks: int):
+    _check(ctx, lib.csp_set_blocks(ctx, blocks))
+
+
+# --- convenience ------------------------------------------------------------
+
+@dataclass
+class DeviceInstance:
+    """An instance resident in device memory (torch uint8 tensors)."""
+    d: int
+    n: int
+    f1: object
+    f2: object
+    A: object
+    B: object
+    M: int
+
+    @property
+    def N(self):
+        return self.n ** self.d
+
+
+def to_device(inst, device="cuda"):
+    import torch
+    t = lambda a: torch.from_numpy(a).to(device)
+    return DeviceInstance(inst.d, inst.n, t(inst.f1), t(inst.f2), t(inst.A), t(inst.B), int(inst.M))
+
+
+class Solver:
+    """Owns one libcsp context on a device."""
+
+    def __init__(self, device: int = 0):
+        self.ctx = csp_create(device)
+        self.device = device
+
+    def close(self):
+        if self.ctx:
+            csp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, di: DeviceInstance, labels=None, M=None, max_cycles=0, stream=None):
+        return csp_solve_dev(self.ctx, di.d, di.n, di.f1, di.f2, di.A, di.B,
+                             di.M if M is None else M, labels=labels,
+                             max_cycles=max_cycles, stream=stream)
+
+    def reconstruct(self, di: DeviceInstance, scratch_mask, cap=None, stream=None):
+        cap = cap if cap is not None else di.N + 1
+        return csp_reconstruct_dev(self.ctx, di.d, di.n, di.f1, di.f2, di.A, di.B, di.M,
+                                   scratch_mask, cap, stream=stream)

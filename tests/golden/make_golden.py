@@ -1,0 +1,59 @@
+"""Write the oracle's expected outputs for the large lattice workloads.
+
+Calls only the CPU oracle (oracle/) and the seeded input generator; nothing
+here touches the HIP library.  Each case is stored as JSON with T, X, x, Y,
+F2, the counters and the SHA-256 of the final labels (uint32, little
+endian).
+
+    python tests/golden/make_golden.py [name ...]
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O                      # noqa: E402
+from paper_1511_06441_amd import inputs as gen      # noqa: E402
+
+
+def cases():
+    out = {}
+    for s in (1, 2, 3):
+        out[f"square64_s{s}"] = lambda s=s: gen.square64(s)
+    for s in (11, 12, 13):
+        for M in (400, 700, 1000):
+            out[f"cube128_s{s}_M{M}"] = lambda s=s, M=M: gen.cube128(s, M)
+    out["cube256_s21"] = lambda: gen.cube256(21)
+    out["cube256stress_s22"] = lambda: gen.cube256_stress(22)
+    return out
+
+
+def labels_sha256(labels) -> str:
+    return hashlib.sha256(labels.astype("<u4").tobytes()).hexdigest()
+
+
+def make(name, builder):
+    inst = builder()
+    t0 = time.time()
+    r = O.solve_instance(inst)
+    dt = time.time() - t0
+    rec = dict(name=name, d=inst.d, n=inst.n, M=inst.M, meta=inst.meta,
+               T=r.T, X=r.X, x=r.x, Y=r.Y, F2=r.F2, counters=r.counters,
+               labels_sha256=labels_sha256(r.labels), oracle_seconds=round(dt, 2))
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(name, r.tuple(), r.counters, f"{dt:.1f}s", flush=True)
+
+
+if __name__ == "__main__":
+    all_cases = cases()
+    names = sys.argv[1:] or list(all_cases)
+    for nm in names:
+        make(nm, all_cases[nm])

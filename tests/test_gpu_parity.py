@@ -1,0 +1,281 @@
+"""HIP path vs the CPU oracle: T, X, x, Y, F2, every final label and every
+counter must match exactly (all arithmetic is integer).
+
+Small and ragged lattices run the oracle in-process; the 128^3 and 256^3
+workloads compare against stored oracle outputs (tests/golden/*.json,
+written by tests/golden/make_golden.py, which calls only the oracle).
+"""
+import glob
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1511_06441_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def solver(torch):
+    from paper_1511_06441_amd import csp
+    s = csp.Solver(0)
+    yield s
+    s.close()
+
+
+def gpu_solve(solver, torch, inst, blocks=0, **kw):
+    from paper_1511_06441_amd import csp
+    di = csp.to_device(inst)
+    lab = torch.zeros(inst.N, dtype=torch.int32, device="cuda")
+    csp.csp_set_blocks(solver.ctx, blocks)
+    try:
+        res, cnt = solver.solve(di, labels=lab, **kw)
+    finally:
+        csp.csp_set_blocks(solver.ctx, 0)
+    torch.cuda.synchronize()
+    return res, cnt, lab.cpu().numpy().view(np.uint32)
+
+
+def _oracle(inst):
+    from oracle import oracle as O
+    return O.solve_instance(inst)
+
+
+def _compare(inst, res, cnt, lab, ref):
+    assert res.tuple() == ref.tuple(), (inst.name, res.tuple(), ref.tuple())
+    assert cnt.asdict() == ref.counters, (inst.name, cnt.asdict(), ref.counters)
+    bad = np.nonzero(lab != ref.labels)[0]
+    assert bad.size == 0, (inst.name, bad[:10], lab[bad[:10]], ref.labels[bad[:10]])
+
+
+def _corner(d, n, seed, K, M):
+    inst = gen.opposite_faces(d, n, seed, K, K, M)
+    inst.A = np.zeros(inst.N, np.uint8)
+    inst.A[0] = 1
+    inst.B = np.zeros(inst.N, np.uint8)
+    inst.B[inst.N - 1] = 1
+    inst.name = f"corner_d{d}_n{n}_s{seed}"
+    return inst
+
+
+SMALL = [
+    # (d, n, seed, K1, K2, M, f1_const, f2_const)
+    (1, 2, 1, 5, 5, 10, None, None),
+    (1, 3, 2, 5, 5, 4, None, None),
+    (1, 50, 3, 9, 9, 200, None, None),
+    (2, 2, 4, 3, 3, 7, None, None),
+    (2, 3, 5, 4, 4, 9, None, None),
+    (2, 5, 6, 5, 5, 20, None, None),
+    (2, 17, 7, 5, 5, 60, None, None),
+    (2, 17, 8, 5, 5, 5, None, None),          # infeasible
+    (2, 31, 9, 255, 255, 3000, None, None),   # long timers, wide wheel
+    (2, 40, 10, 1, 3, 100, 1, None),          # unit times
+    (2, 23, 11, 1, 1, 50, 1, 1),              # all ones: ties everywhere
+    (3, 2, 12, 5, 5, 20, None, None),
+    (3, 3, 13, 7, 7, 30, None, None),
+    (3, 7, 14, 10, 10, 60, None, None),
+    (3, 20, 15, 10, 10, 150, None, None),
+    (3, 33, 16, 10, 10, 300, None, None),
+    (4, 3, 17, 4, 4, 20, None, None),
+    (4, 5, 18, 6, 6, 40, None, None),
+    (4, 9, 19, 8, 8, 80, None, None),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"d{c[0]}n{c[1]}s{c[2]}M{c[5]}" for c in SMALL])
+def test_small_vs_oracle(solver, torch, case):
+    d, n, seed, K1, K2, M, c1, c2 = case
+    inst = gen.opposite_faces(d, n, seed, K1, K2, M, f1_const=c1, f2_const=c2)
+    inst.name = f"d{d}n{n}s{seed}M{M}"
+    _say("case", inst.name)
+    ref = _oracle(inst)
+    res, cnt, lab = gpu_solve(solver, torch, inst)
+    _compare(inst, res, cnt, lab, ref)
+
+
+@pytest.mark.parametrize("blocks", [1, 2, 3, 8, 64])
+@pytest.mark.parametrize("which", ["square", "cube", "corner"])
+def test_block_counts_vs_oracle(solver, torch, blocks, which):
+    """Multi-block grids (grid barrier, cross-block queues) on small inputs."""
+    if which == "square":
+        inst = gen.square64(2)
+    elif which == "cube":
+        inst = gen.opposite_faces(3, 24, 5, 10, 10, 200)
+        inst.name = "cube24"
+    else:
+        inst = _corner(3, 12, 3, 6, 150)
+    _say("case", inst.name, "blocks", blocks)
+    ref = _oracle(inst)
+    res, cnt, lab = gpu_solve(solver, torch, inst, blocks=blocks)
+    _compare(inst, res, cnt, lab, ref)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_square64_vs_oracle(solver, torch, seed):
+    inst = gen.square64(seed)
+    _say("case", inst.name)
+    ref = _oracle(inst)
+    res, cnt, lab = gpu_solve(solver, torch, inst)
+    _compare(inst, res, cnt, lab, ref)
+
+
+def test_corner_and_boundary_shapes(solver, torch):
+    for inst in (_corner(2, 30, 1, 5, 80), _corner(3, 10, 2, 5, 60),
+                 gen.cube_boundary_to_center(20, 4, K=100, M=3000)):
+        _say("case", inst.name)
+        ref = _oracle(inst)
+        res, cnt, lab = gpu_solve(solver, torch, inst)
+        _compare(inst, res, cnt, lab, ref)
+
+
+def test_empty_A(solver, torch):
+    inst = gen.square64(1)
+    inst.A = np.zeros(inst.N, np.uint8)
+    res, cnt, lab = gpu_solve(solver, torch, inst)
+    assert res.tuple() == (-1, -1, -1, -1, -1) and lab.max() == 0
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads against stored oracle outputs
+# ---------------------------------------------------------------------------
+
+def _golden_cases():
+    out = []
+    for f in sorted(glob.glob(os.path.join(GOLDEN, "cube*.json"))):
+        out.append(os.path.basename(f)[:-5])
+    return out
+
+
+def _build(rec):
+    nm = rec["name"]
+    if nm.startswith("cube128"):
+        return gen.cube128(rec["meta"]["seed"], rec["M"])
+    if nm.startswith("cube256stress"):
+        return gen.cube256_stress(rec["meta"]["seed"], rec["M"])
+    if nm.startswith("cube256"):
+        return gen.cube256(rec["meta"]["seed"], rec["M"])
+    raise KeyError(nm)
+
+
+@pytest.mark.parametrize("name", _golden_cases())
+def test_full_size_vs_stored_oracle(solver, torch, name):
+    with open(os.path.join(GOLDEN, name + ".json")) as fh:
+        rec = json.load(fh)
+    inst = _build(rec)
+    _say("case", name)
+    res, cnt, lab = gpu_solve(solver, torch, inst)
+    assert res.tuple() == (rec["T"], rec["X"], rec["x"], rec["Y"], rec["F2"])
+    assert cnt.asdict() == rec["counters"]
+    assert hashlib.sha256(lab.astype("<u4").tobytes()).hexdigest() == rec["labels_sha256"]
+
+
+def test_stress_closed_form(solver, torch):
+    """f1 == 1 on the 256^3 cube: only straight axis-0 lines arrive by 255."""
+    from tests import pins
+    inst = gen.cube256_stress(22)
+    _say("case", inst.name)
+    res, cnt, lab = gpu_solve(solver, torch, inst)
+    assert res.tuple() == pins.straight_line_answer(3, 256, inst.f2)
+
+
+# ---------------------------------------------------------------------------
+# determinism, retries, errors, host-pointer entry, path recovery
+# ---------------------------------------------------------------------------
+
+def test_repeat_runs_identical(solver, torch):
+    inst = gen.cube128(12, 700)
+    r1, c1, l1 = gpu_solve(solver, torch, inst)
+    r2, c2, l2 = gpu_solve(solver, torch, inst)
+    assert r1.tuple() == r2.tuple() and c1.asdict() == c2.asdict() and np.array_equal(l1, l2)
+
+
+def test_pool_overflow_retry_gives_same_result(solver, torch):
+    from paper_1511_06441_amd import csp
+    inst = gen.square64(3)
+    ref = _oracle(inst)
+    csp.csp_set_pool_hint(solver.ctx, 16)
+    try:
+        res, cnt, lab = gpu_solve(solver, torch, inst, blocks=4)
+    finally:
+        csp.csp_set_pool_hint(solver.ctx, 0)
+    _compare(inst, res, cnt, lab, ref)
+
+
+def test_cycle_cap_cancels(solver, torch):
+    from paper_1511_06441_amd import csp
+    inst = gen.square64(1)
+    with pytest.raises(csp.CspError) as e:
+        gpu_solve(solver, torch, inst, max_cycles=5)
+    assert e.value.code == csp.CSP_ECANCELED
+    res, cnt, lab = gpu_solve(solver, torch, inst)          # context still usable
+    assert res.T == 142
+
+
+def test_invalid_inputs_rejected(solver, torch):
+    from paper_1511_06441_amd import csp
+    base = gen.opposite_faces(2, 8, 1, 5, 5, 30)
+
+    def expect_einval(inst, d=None, n=None, M=None):
+        di = csp.to_device(inst)
+        with pytest.raises(csp.CspError) as e:
+            csp.csp_solve_dev(solver.ctx, d or inst.d, n or inst.n, di.f1, di.f2, di.A, di.B,
+                              inst.M if M is None else M)
+        assert e.value.code == csp.CSP_EINVAL
+
+    bad = gen.opposite_faces(2, 8, 1, 5, 5, 30)
+    bad.B = bad.A.copy()
+    expect_einval(bad)                                       # A and B overlap
+    bad = gen.opposite_faces(2, 8, 1, 5, 5, 30)
+    bad.f2[3] = 0
+    expect_einval(bad)                                       # zero weight on a real edge
+    expect_einval(base, M=0)
+    expect_einval(base, M=csp.CSP_MAX_M + 1)
+    expect_einval(base, d=5)
+    expect_einval(base, n=1)
+    # a zero on a padding entry is fine
+    ok = gen.opposite_faces(2, 8, 1, 5, 5, 30)
+    assert ok.f1[7] == 0
+    gpu_solve(solver, torch, ok)
+
+
+def test_host_pointer_entry(solver, torch):
+    from paper_1511_06441_amd import csp
+    inst = gen.square64(2)
+    ref = _oracle(inst)
+    lab = np.zeros(inst.N, np.uint32)
+    res, cnt = csp.csp_solve(solver.ctx, inst.d, inst.n, inst.f1, inst.f2, inst.A, inst.B, inst.M, lab)
+    _compare(inst, res, cnt, lab, ref)
+
+
+@pytest.mark.parametrize("case", [(2, 12, 1, 5, 5, 50), (3, 6, 3, 10, 10, 60), (2, 64, 2, 5, 5, 200),
+                                  (3, 16, 4, 10, 10, 150)])
+def test_reconstruct_vs_oracle(solver, torch, case):
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    d, n, seed, K1, K2, M = case
+    inst = gen.opposite_faces(d, n, seed, K1, K2, M)
+    path_ref, res_ref, _ = O.reconstruct(d, n, inst.f1, inst.f2, inst.A, inst.B, M)
+    di = csp.to_device(inst)
+    scratch = torch.zeros(inst.N, dtype=torch.uint8, device="cuda")
+    path, res = solver.reconstruct(di, scratch)
+    assert res.tuple() == res_ref.tuple()
+    assert path.tolist() == path_ref.tolist()
+    assert int(scratch.sum().item()) == 0
