@@ -19,14 +19,35 @@
 //             in bucket (t + f1) mod W.  Delivered flows simply leave their
 //             bucket (Steps 7, 9).
 //
-// Step 1's time skip is the first non-empty bucket after t.  Both phases run
-// inside one persistent cooperative kernel separated by a grid barrier.
+// Step 1's time skip is the first non-empty bucket after t.
 //
-// Label words pack (label << 1) | idle: idle = 1 means "not yet appended to
-// this cycle's improved set".  A delivery does atomicMax(word, q << 1), which
-// raises the label and clears the idle bit in one operation; the returned
-// old word tells the thread whether it raised the label and whether it was
-// the first to do so this cycle.  Departure sets the idle bit again.
+// Layout and synchronisation, chosen for the cost profile of MI355X (device
+// atomics on one address serialise at ~11 ns each; a grid-wide barrier costs
+// microseconds and grows with the number of participants):
+//
+//  * One persistent cooperative kernel, one 1024-thread workgroup per CU.
+//  * Each workgroup owns a private segment of every wheel bucket and fills it
+//    with LDS counters; it later delivers exactly the flows it filed, so the
+//    wheel needs no device-wide counter at all.
+//  * Each workgroup appends the vertices it improved to a private frontier
+//    segment.  After the arrival barrier every workgroup reads all segment
+//    sizes, prefix-sums them in LDS and departs an equal slice of the
+//    concatenation, so the departure work is balanced every cycle.
+//  * The next event time is the minimum of per-workgroup minima published
+//    before the departure barrier.
+//  * The grid barrier is a two-level counter tree (one group per XCD) with
+//    one release flag per workgroup, so no address sees more than ~32 atomics
+//    and every waiter spins on its own cache line.
+//  * Label words pack (label << 2) | inB << 1 | idle.  idle = 1 means "not yet
+//    in this cycle's improved set".  A delivery does atomicMax(word, q << 2),
+//    which raises the label and clears idle and inB at once; the returned old
+//    word says whether this thread raised the label first this cycle and
+//    whether the vertex is in B.  Departure writes the word back with both
+//    bits restored.
+//  * Edge times are repacked per vertex: record v holds (f1, f2) of its 2d
+//    incident edges in direction order (zero where the lattice ends), so a
+//    departure reads one 4/8/16-byte record instead of 4d scattered bytes and
+//    needs no coordinate arithmetic.
 //
 // All arithmetic is integer; results are bit-identical to the CPU oracle.
 
@@ -41,45 +62,51 @@
 
 namespace {
 
-constexpr int BLOCK = 256;
+constexpr int BLOCK = 1024;
+constexpr int NWAVES = BLOCK / 64;
 constexpr int MAXW = 256;          // f1 <= 255, so 256 buckets always suffice
+constexpr int GMAX = 512;          // workgroups per launch
+constexpr int NGRP = 8;            // barrier groups (one per XCD)
 constexpr unsigned IDLE = 1u;
+constexpr unsigned INB = 2u;
+constexpr unsigned QB_INB = 0x80000000u;   // frontier entry: vertex is in B
 
-// Control block in device memory: bucket fill counts, queue sizes, barrier
-// state, termination reductions and counters.
+// slot flags
+constexpr unsigned SF_BHIT = 1u << 31;
+constexpr unsigned SF_OVER = 1u << 30;
+constexpr unsigned SF_INVAL = 1u << 29;
+constexpr unsigned SF_MASK = 0x1FFFFFFFu;
+
 struct Ctl {
-    unsigned cnt[MAXW];
-    unsigned qcount[2];
-    unsigned bar_count;
-    unsigned bar_gen;
-    unsigned bhit;
-    unsigned ydir;
+    unsigned grp[NGRP][32];        // barrier group counters, one per 128-byte line
+    unsigned root[32];
+    unsigned flag[GMAX][32];       // per-workgroup release flags
+    unsigned qslot[GMAX];          // arrival: frontier size | flags
+    unsigned nslot[GMAX];          // departure: next delta (0 = none) | flags
+    unsigned tslot[GMAX];          // departure: flows in transit
     unsigned long long xkey;
+    unsigned ydir;
+    unsigned bad;                  // set by the packing kernel
+    unsigned maxf1;
+    unsigned pad0;
     unsigned long long ctr[8];     // C U D E R P I
     long long res[5];              // T X x Y F2
     int status;
-    int broken;                    // a barrier wait timed out
+    int broken;
 };
 
-enum { ST_RUNNING = 0, ST_DONE = 1, ST_OVERFLOW = 2, ST_CANCELED = 3, ST_BROKEN = 4 };
-
-struct Info {
-    unsigned bad;
-    unsigned maxf1;
-    unsigned nA;
-    unsigned pad;
-};
+enum { ST_RUNNING = 0, ST_DONE = 1, ST_OVERFLOW = 2, ST_CANCELED = 3, ST_BROKEN = 4, ST_INVAL = 5 };
 
 struct Params {
-    long long n, N;
-    long long stride[4];
-    const uint8_t *f1, *f2, *A, *B;
+    long long N;
+    long long off[8];              // neighbour offset per direction
+    const void *rec;               // packed (f1, f2) per vertex and direction
+    const uint8_t *A, *B;
     unsigned M;
-    unsigned W;                    // power of two > max f1
-    unsigned long long cap;        // flows per bucket
+    unsigned qs;                   // frontier capacity per workgroup
+    unsigned long long pool_flows; // total wheel capacity in flows
     unsigned *lab;
-    unsigned *queue0, *queue1;
-    unsigned *bhitv;
+    unsigned *queue;               // [G][qs]
     uint2 *pool;
     Ctl *ctl;
     unsigned *labels_out;
@@ -87,125 +114,139 @@ struct Params {
     unsigned long long wait_limit; // wall-clock ticks a barrier wait may take
 };
 
+// record type per dimension: 2d (f1, f2) byte pairs
+template <int D> struct Rec;
+template <> struct Rec<1> { using T = uint32_t; };
+template <> struct Rec<2> { using T = uint2; };
+template <> struct Rec<3> { using T = uint4; };
+template <> struct Rec<4> { using T = uint4; };
+
+template <int D>
+__device__ __forceinline__ void rec_get(const typename Rec<D>::T &r, int dir, unsigned &a1, unsigned &a2)
+{
+    unsigned w;
+    if constexpr (D == 1) {
+        w = r;
+    } else if constexpr (D == 2) {
+        w = dir < 2 ? r.x : r.y;
+    } else {
+        const int q = dir >> 1;
+        w = q == 0 ? r.x : (q == 1 ? r.y : (q == 2 ? r.z : r.w));
+    }
+    const unsigned sh = (dir & 1) ? 16u : 0u;
+    const unsigned pr = (D == 1) ? (w >> (16u * dir)) : (w >> sh);
+    a1 = pr & 0xFFu;
+    a2 = (pr >> 8) & 0xFFu;
+}
+
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ unsigned ld_acq(const unsigned *p)
+__device__ __forceinline__ unsigned ld_rlx(const unsigned *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ unsigned long long ld_acq64(const unsigned long long *p)
+__device__ __forceinline__ void st_rlx(unsigned *p, unsigned v)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Append pred-true lanes of a wavefront to a global list with one atomic.
-__device__ __forceinline__ bool wave_append(unsigned *counter, bool pred, unsigned &slot)
-{
-    const unsigned long long m = __ballot(pred);
-    if (m == 0) return false;
-    const int lead = __ffsll((long long)m) - 1;
-    const int lane = __lane_id();
-    unsigned base = 0;
-    if (lane == lead)
-        base = __hip_atomic_fetch_add(counter, (unsigned)__popcll(m), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-    base = __shfl(base, lead);
-    slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
-    return pred;
-}
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
-// Sense-counting grid barrier for a cooperative launch (all blocks are
-// co-resident, so every wait ends).  Thread 0 of each block arrives with a
-// release and waits with an acquire at agent scope; the block barriers
-// around it extend that ordering to the whole block.  A wait that outlasts
-// `limit` wall-clock ticks marks the run broken and returns false, so a
+// Two-level tree barrier over a cooperative grid.  Thread 0 of each
+// workgroup publishes the group's writes with an agent-scope release fence
+// and counts itself in its XCD group; the last arriver of a group counts the
+// group at the root; the last group releases every workgroup by writing the
+// new epoch into its private flag line.  Waiters spin on their own flag and
+// finish with an acquire fence.  Every wait is bounded by `limit` wall-clock
+// ticks; on expiry the run is marked broken and the call returns false, so a
 // logic error drains the grid instead of hanging it.
-__device__ __forceinline__ bool grid_barrier(Ctl *ctl, unsigned &gen, unsigned long long limit)
+__device__ bool grid_sync(Ctl *ctl, unsigned &epoch, unsigned long long limit)
 {
     __shared__ int s_ok;
     __syncthreads();
-    if (gridDim.x > 1) {
+    ++epoch;
+    const unsigned G = gridDim.x;
+    if (G == 1) return true;
+    if (threadIdx.x < 64) {
+        int releaser = 0;
         if (threadIdx.x == 0) {
-            int ok = 1;
-            const unsigned g = gen;
-            const unsigned arrived = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-            if (arrived == gridDim.x - 1) {
-                __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&ctl->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                const unsigned long long t0 = wall_clock64();
-                while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (wall_clock64() - t0 > limit) {
-                        __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ok = 0;
-                        break;
-                    }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned grp = blockIdx.x % NGRP;
+            const unsigned ngrp = G < NGRP ? G : NGRP;
+            const unsigned members = (G - grp + NGRP - 1) / NGRP;
+            const unsigned a = __hip_atomic_fetch_add(&ctl->grp[grp][0], 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (a == members - 1) {
+                st_rlx(&ctl->grp[grp][0], 0u);
+                const unsigned r = __hip_atomic_fetch_add(&ctl->root[0], 1u, __ATOMIC_ACQ_REL,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (r == ngrp - 1) {
+                    st_rlx(&ctl->root[0], 0u);
+                    releaser = 1;
                 }
             }
+        }
+        releaser = __shfl(releaser, 0);
+        if (releaser) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (unsigned i = threadIdx.x; i < G; i += 64) st_rlx(&ctl->flag[i][0], epoch);
+        }
+        if (threadIdx.x == 0) {
+            int ok = 1;
+            const unsigned long long t0 = wall_clock64();
+            while (ld_rlx(&ctl->flag[blockIdx.x][0]) < epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - t0 > limit) {
+                    __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (__hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
             s_ok = ok;
         }
-        gen += 1;
-    } else if (threadIdx.x == 0) {
-        s_ok = 1;
     }
     __syncthreads();
     return s_ok != 0;
 }
 
+// Exclusive prefix sum over one value per thread (BLOCK threads); returns
+// the exclusive prefix and writes the total to *total (all threads).
+__device__ unsigned block_scan(unsigned v, unsigned *s_wave, unsigned *total)
+{
+    const unsigned lane = lane_id(), wv = threadIdx.x >> 6;
+    unsigned x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o);
+        if (lane >= (unsigned)o) x += y;
+    }
+    if (lane == 63) s_wave[wv] = x;
+    __syncthreads();
+    if (wv == 0) {
+        unsigned w = lane < NWAVES ? s_wave[lane] : 0u;
+#pragma unroll
+        for (int o = 1; o < NWAVES; o <<= 1) {
+            const unsigned y = __shfl_up(w, o);
+            if (lane >= (unsigned)o) w += y;
+        }
+        if (lane < NWAVES) s_wave[lane] = w;      // inclusive wave totals
+    }
+    __syncthreads();
+    const unsigned before = wv ? s_wave[wv - 1] : 0u;
+    *total = s_wave[NWAVES - 1];
+    const unsigned r = before + x - v;
+    __syncthreads();
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-
-// Input checks: positive f on real edges, A and B disjoint; also the largest
-// f1 (sizes the wheel) and |A|.
-__global__ void __launch_bounds__(BLOCK) k_validate(int d, long long n, long long N,
-                                                    const uint8_t *f1, const uint8_t *f2,
-                                                    const uint8_t *A, const uint8_t *B, Info *info)
-{
-    const long long gsize = (long long)gridDim.x * BLOCK;
-    const long long gtid = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    unsigned bad = 0, mx = 0, na = 0;
-    for (long long i = gtid; i < (long long)d * N; i += gsize) {
-        const long long k = i / N, u = i - k * N;
-        long long s = 1;
-        for (long long j = 0; j < k; ++j) s *= n;
-        const long long c = (u / s) % n;
-        if (c < n - 1) {
-            const unsigned a = f1[i], b = f2[i];
-            if (a == 0 || b == 0) bad |= 1u;
-            mx = a > mx ? a : mx;
-        }
-    }
-    for (long long v = gtid; v < N; v += gsize) {
-        const bool a = A[v] != 0;
-        if (a && B[v] != 0) bad |= 2u;
-        na += a;
-    }
-    // wave reductions, then one atomic per wave
-    for (int o = 32; o > 0; o >>= 1) {
-        bad |= __shfl_xor(bad, o);
-        mx = max(mx, (unsigned)__shfl_xor(mx, o));
-        na += __shfl_xor(na, o);
-    }
-    if (__lane_id() == 0) {
-        if (bad) atomicOr(&info->bad, bad);
-        if (mx) atomicMax(&info->maxf1, mx);
-        if (na) atomicAdd(&info->nA, na);
-    }
-}
-
-__global__ void k_zero_info(Info *info)
-{
-    info->bad = 0;
-    info->maxf1 = 0;
-    info->nA = 0;
-}
 
 // Clear the control block (a kernel rather than a memset, so the sequence
 // stays valid inside captured graphs).
@@ -217,216 +258,360 @@ __global__ void __launch_bounds__(BLOCK) k_reset_ctl(Ctl *ctl)
     if (threadIdx.x == 0) ctl->ydir = 0xFFFFFFFFu;
 }
 
+// Repack SoA edge arrays into per-vertex records of 2d (f1, f2) pairs in
+// direction order (-n^(d-1) .. -1, +1 .. +n^(d-1)); zero where no edge.
+// Also checks that every real edge has positive f1 and f2 and records the
+// largest f1 (it sizes the timing wheel).
+template <int D>
+__global__ void __launch_bounds__(256) k_pack(long long n, long long N, const uint8_t *f1,
+                                              const uint8_t *f2, typename Rec<D>::T *rec, Ctl *ctl)
+{
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    unsigned bad = 0, mx = 0;
+    long long stride[D];
+    {
+        long long s = 1;
+        for (int k = 0; k < D; ++k) {
+            stride[k] = s;
+            s *= n;
+        }
+    }
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gs) {
+        long long c[D];
+        long long rem = v;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            c[k] = rem % n;
+            rem /= n;
+        }
+        unsigned pr[2 * D];
+#pragma unroll
+        for (int dir = 0; dir < 2 * D; ++dir) {
+            const bool lower = dir < D;
+            const int k = lower ? D - 1 - dir : dir - D;
+            const bool exists = lower ? (c[k] >= 1) : (c[k] <= n - 2);
+            pr[dir] = 0;
+            if (exists) {
+                const long long e = (long long)k * N + (lower ? v - stride[k] : v);
+                const unsigned a = f1[e], b = f2[e];
+                if (a == 0 || b == 0) bad = 1;
+                mx = a > mx ? a : mx;
+                pr[dir] = a | (b << 8);
+            }
+        }
+        typename Rec<D>::T r;
+        if constexpr (D == 1) {
+            r = pr[0] | (pr[1] << 16);
+        } else if constexpr (D == 2) {
+            r = make_uint2(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16));
+        } else if constexpr (D == 3) {
+            r = make_uint4(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16), pr[4] | (pr[5] << 16), 0u);
+        } else {
+            r = make_uint4(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16), pr[4] | (pr[5] << 16),
+                           pr[6] | (pr[7] << 16));
+        }
+        rec[v] = r;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        bad |= __shfl_xor(bad, o);
+        mx = max(mx, (unsigned)__shfl_xor(mx, o));
+    }
+    if (lane_id() == 0) {
+        if (bad) atomicOr(&ctl->bad, 1u);
+        if (mx) atomicMax(&ctl->maxf1, mx);
+    }
+}
+
 template <int D>
 __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
 {
-    __shared__ unsigned s_cnt[MAXW];
-    __shared__ unsigned s_base[MAXW];
-    __shared__ long long s_next;
-    __shared__ unsigned long long s_red[3];
+    using RT = typename Rec<D>::T;
+    __shared__ unsigned s_cnt[MAXW];           // this workgroup's fill per bucket
+    __shared__ unsigned s_pref[GMAX + 1];      // frontier prefix sums over workgroups
+    __shared__ unsigned s_wave[NWAVES];
+    __shared__ unsigned s_qn;                  // this workgroup's frontier fill
+    __shared__ unsigned s_flags;
+    __shared__ unsigned s_min;
+    __shared__ unsigned long long s_red[4];
 
     Ctl *ctl = p.ctl;
-    const unsigned tid = threadIdx.x;
-    const bool lead_block = blockIdx.x == 0;
-    const unsigned long long gsize = (unsigned long long)gridDim.x * BLOCK;
-    const unsigned long long gtid = (unsigned long long)blockIdx.x * BLOCK + tid;
-    const unsigned Wm = p.W - 1;
-    const long long n = p.n, N = p.N;
-    unsigned gen = 0;
-    bool status_init_broken = false;
+    const unsigned tid = threadIdx.x, lane = lane_id();
+    const unsigned g = blockIdx.x, G = gridDim.x;
+    const bool lead = g == 0;
+    const long long N = p.N;
+    const RT *rec = static_cast<const RT *>(p.rec);
+    unsigned epoch = 0;
 
-    unsigned long long cU = 0, cD = 0, cE = 0;           // per thread
-    unsigned long long cC = 0, cR = 0, cP = 0, cI = 0;   // thread 0 of block 0
+    unsigned W = 2;
+    while (W <= ctl->maxf1) W <<= 1;
+    const unsigned Wm = W - 1;
+    const unsigned long long S = p.pool_flows / ((unsigned long long)W * G);   // flows per segment
+    const unsigned QS = p.qs;
+    unsigned *myq = p.queue + (unsigned long long)g * QS;
+
+    unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread
+    unsigned long long cC = 0, cP = 0, cI = 0;              // lead workgroup, thread 0
+
+    for (unsigned i = tid; i < MAXW; i += BLOCK) s_cnt[i] = 0;
+    if (tid == 0) {
+        s_qn = 0;
+        s_flags = 0;
+        for (int i = 0; i < 4; ++i) s_red[i] = 0;
+    }
+    __syncthreads();
+
+    int status = ST_RUNNING;
+    if (ctl->bad) status = ST_INVAL;                       // read by every workgroup alike
 
     // ---- Initialization (Algorithm 3): Label = M on A, 0 elsewhere; A is I_0.
-    for (unsigned long long v = gtid; v < (unsigned long long)N; v += gsize) {
-        const bool a = p.A[v] != 0;
-        p.lab[v] = a ? ((p.M << 1) | IDLE) : IDLE;
-        unsigned slot;
-        if (wave_append(&ctl->qcount[0], a, slot)) p.queue0[slot] = (unsigned)v;
+    if (status == ST_RUNNING) {
+        const long long chunk = (N + G - 1) / G;
+        const long long lo = (long long)g * chunk, hi = min(N, lo + chunk);
+        for (long long v = lo + tid; v < hi; v += BLOCK) {
+            const bool a = p.A[v] != 0, b = p.B[v] != 0;
+            if (a && b) atomicOr(&s_flags, SF_INVAL);
+            p.lab[v] = (a ? (p.M << 2) : 0u) | (b ? INB : 0u) | IDLE;
+            const unsigned long long m = __ballot(a);
+            if (m) {
+                const int ld = __ffsll((long long)m) - 1;
+                unsigned base = 0;
+                if ((int)lane == ld) base = atomicAdd(&s_qn, (unsigned)__popcll(m));
+                base = __shfl(base, ld);
+                const unsigned slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+                if (a) myq[slot] = (unsigned)v;                   // chunk <= QS
+            }
+        }
+        __syncthreads();
+        if (tid == 0) st_rlx(&ctl->qslot[g], s_qn | s_flags);
     }
-    if (!grid_barrier(ctl, gen, p.wait_limit)) status_init_broken = true;
-    {
-        const unsigned nA = ld_acq(&ctl->qcount[0]);
-        cU += (gtid == 0) ? nA : 0;
-    }
+    if (status == ST_RUNNING && !grid_sync(ctl, epoch, p.wait_limit)) status = ST_BROKEN;
 
     long long t = 0;
     unsigned cyc = 0;
-    int status = status_init_broken ? ST_BROKEN : ST_RUNNING;
-    unsigned b_last = 0, nb_last = 0;
+    unsigned bucket_n = 0;      // flows this workgroup delivered in the last arrival
+    unsigned b_cur = 0;
+    unsigned Qtot = 0;
+
+    // frontier sizes -> prefix sums (every workgroup computes the same)
+    auto gather_frontier = [&](unsigned &flags) {
+        const unsigned raw = tid < G ? ld_rlx(&ctl->qslot[tid]) : 0u;
+        const unsigned v = raw & SF_MASK;
+        const unsigned fl = __syncthreads_or((int)(raw & ~SF_MASK)) ? 1u : 0u;
+        unsigned any = 0;
+        if (fl) {
+            if (tid == 0) s_min = 0;
+            __syncthreads();
+            if (raw & ~SF_MASK) atomicOr(&s_min, raw & ~SF_MASK);
+            __syncthreads();
+            any = s_min;
+            __syncthreads();
+        }
+        unsigned total;
+        const unsigned ex = block_scan(v, s_wave, &total);
+        if (tid < G) s_pref[tid] = ex;
+        if (tid == 0) s_pref[G] = total;
+        __syncthreads();
+        flags = any;
+        return total;
+    };
+
+    if (status == ST_RUNNING) {
+        unsigned fl;
+        Qtot = gather_frontier(fl);
+        if (fl & SF_INVAL) status = ST_INVAL;
+        cU += (g == 0 && tid == 0) ? Qtot : 0;
+    }
 
     while (status == ST_RUNNING) {
-        // ---- Departure (Steps 4-5, Algorithms 7-8) from I_t.
-        const unsigned par = cyc & 1u;
-        const unsigned *queue = par ? p.queue1 : p.queue0;
-        const unsigned nq = ld_acq(&ctl->qcount[par]);
-        if (lead_block && tid == 0) {
-            __hip_atomic_store(&ctl->qcount[par ^ 1u], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->cnt[t & Wm], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const unsigned long long rounds = (nq + gsize - 1) / gsize;
-        for (unsigned long long r = 0; r < rounds; ++r) {
-            for (unsigned b = tid; b < p.W; b += BLOCK) s_cnt[b] = 0;
-            __syncthreads();
-            // one slot per direction keeps the arrays in registers
-            unsigned eb[2 * D], epos[2 * D], edst[2 * D], ekey[2 * D];
+        // ---- Departure (Steps 4-5, Algorithms 7-8): an equal slice of I_t.
+        {
+            const unsigned lo = (unsigned)(((unsigned long long)Qtot * g) / G);
+            const unsigned hi = (unsigned)(((unsigned long long)Qtot * (g + 1)) / G);
+            for (unsigned i = lo + tid; i < hi; i += BLOCK) {
+                // segment s with s_pref[s] <= i < s_pref[s+1]
+                unsigned a = 0, b = G;
+                while (b - a > 1) {
+                    const unsigned m = (a + b) >> 1;
+                    if (s_pref[m] <= i) a = m;
+                    else b = m;
+                }
+                const unsigned e = p.queue[(unsigned long long)a * QS + (i - s_pref[a])];
+                const unsigned Q = e & ~QB_INB;
+                const unsigned L = p.lab[Q] >> 2;
+                p.lab[Q] = (L << 2) | ((e & QB_INB) ? INB : 0u) | IDLE;
+                const RT r = rec[Q];
+                unsigned lp[2 * D];
 #pragma unroll
-            for (int dir = 0; dir < 2 * D; ++dir) eb[dir] = 0xFFFFFFFFu;
-            const unsigned long long idx = r * gsize + gtid;
-            if (idx < nq) {
-                const unsigned Q = queue[idx];
-                const unsigned w = p.lab[Q];
-                const long long L = (long long)(w >> 1);
-                p.lab[Q] = w | IDLE;
-                long long c[D];
-                {
-                    long long rem = Q;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        c[k] = rem % n;
-                        rem /= n;
-                    }
+                for (int dir = 0; dir < 2 * D; ++dir) {
+                    unsigned a1, a2;
+                    rec_get<D>(r, dir, a1, a2);
+                    lp[dir] = a1 ? p.lab[(long long)Q + p.off[dir]] : 0xFFFFFFFFu;
                 }
 #pragma unroll
                 for (int dir = 0; dir < 2 * D; ++dir) {
-                    // direction codes ascend with the neighbour's index:
-                    // -n^(D-1) .. -1, +1 .. +n^(D-1)
-                    const bool lower = dir < D;
-                    const int k = lower ? D - 1 - dir : dir - D;
-                    const bool exists = lower ? (c[k] >= 1) : (c[k] <= n - 2);
-                    if (exists) {
-                        const long long P = lower ? (long long)Q - p.stride[k] : (long long)Q + p.stride[k];
-                        const long long e = (long long)k * N + (lower ? P : (long long)Q);
-                        const unsigned a1 = p.f1[e], a2 = p.f2[e];
+                    unsigned a1, a2;
+                    rec_get<D>(r, dir, a1, a2);
+                    if (a1) {
                         ++cD;
-                        const long long q = L - (long long)a2;
-                        const long long Lp = (long long)(p.lab[P] >> 1);
-                        if (q > Lp) {
-                            const unsigned b = (unsigned)((t + a1) & Wm);
-                            eb[dir] = b;
-                            epos[dir] = atomicAdd(&s_cnt[b], 1u);
-                            edst[dir] = (unsigned)P;
-                            // the receiver sees the sender in the opposite direction
-                            ekey[dir] = ((unsigned)q << 3) | (unsigned)(2 * D - 1 - dir);
+                        const int q = (int)L - (int)a2;
+                        if (q > (int)(lp[dir] >> 2)) {
+                            const unsigned bk = (unsigned)((t + a1) & Wm);
+                            const unsigned pos = atomicAdd(&s_cnt[bk], 1u);
+                            if (pos < S) {
+                                // the receiver sees the sender in the opposite direction
+                                p.pool[((unsigned long long)bk * G + g) * S + pos] =
+                                    make_uint2((unsigned)((long long)Q + p.off[dir]),
+                                               ((unsigned)q << 3) | (unsigned)(2 * D - 1 - dir));
+                            } else {
+                                atomicOr(&s_flags, SF_OVER);
+                            }
                             ++cE;
                         }
                     }
                 }
             }
-            __syncthreads();
-            for (unsigned b = tid; b < p.W; b += BLOCK) {
-                const unsigned k = s_cnt[b];
-                if (k) s_base[b] = atomicAdd(&ctl->cnt[b], k);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int dir = 0; dir < 2 * D; ++dir) {
-                if (eb[dir] != 0xFFFFFFFFu) {
-                    const unsigned long long pos = (unsigned long long)s_base[eb[dir]] + epos[dir];
-                    if (pos < p.cap)
-                        p.pool[(unsigned long long)eb[dir] * p.cap + pos] = make_uint2(edst[dir], ekey[dir]);
-                }
-            }
-            __syncthreads();
-        }
-        if (!grid_barrier(ctl, gen, p.wait_limit)) { status = ST_BROKEN; break; }
-
-        // ---- Step 1 (Algorithm 4): next delivery time = first non-empty bucket.
-        if (tid < 64) {
-            long long best = -1;
-            bool over = false;
-            unsigned long long transit = 0;
-            for (unsigned j = tid; j + 1 < p.W; j += 64) {
-                const unsigned c = ld_acq(&ctl->cnt[(t + 1 + j) & Wm]);
-                transit += c;
-                if (c > p.cap) over = true;
-                if (c && best < 0) best = (long long)j;
-            }
-            // smallest j with a non-empty bucket across the wave
-            unsigned long long mbest = __ballot(best >= 0);
-            long long jmin = -1;
-            if (mbest) {
-                // candidates are strided by 64; take the minimum value
-                long long v = best >= 0 ? best : (long long)1 << 40;
-                for (int o = 32; o > 0; o >>= 1) {
-                    const long long ov = __shfl_xor(v, o);
-                    v = ov < v ? ov : v;
-                }
-                jmin = v;
-            }
-            over = __ballot(over) != 0;
-            for (int o = 32; o > 0; o >>= 1) transit += __shfl_xor(transit, o);
-            if (tid == 0) {
-                s_next = over ? -2 : (jmin < 0 ? -1 : t + 1 + jmin);
-                if (lead_block) cP = transit > cP ? transit : cP;
-            }
         }
         __syncthreads();
-        const long long tn = s_next;
-        if (tn == -2) { status = ST_OVERFLOW; break; }
-        if (tn == -1) { status = ST_DONE; break; }                     // condition 2
-        if (p.max_cycles > 0 && (long long)cyc >= p.max_cycles) { status = ST_CANCELED; break; }
-        t = tn;
-        ++cyc;
-        if (lead_block && tid == 0) ++cC;
-
-        // ---- Arrival (Steps 1-3 and 8, Algorithms 4-6, 10).
-        const unsigned npar = cyc & 1u;
-        unsigned *nqueue = npar ? p.queue1 : p.queue0;
-        const unsigned b = (unsigned)(t & Wm);
-        const unsigned nb = ld_acq(&ctl->cnt[b]);
-        const uint2 *bk = p.pool + (unsigned long long)b * p.cap;
-        for (unsigned long long j = gtid; j < nb; j += gsize) {
-            const uint2 f = bk[j];
-            const unsigned P = f.x, q = f.y >> 3;
-            bool imp = false;
-            if (q > (p.lab[P] >> 1)) {
-                const unsigned old = atomicMax(&p.lab[P], q << 1);
-                imp = (q > (old >> 1)) && (old & IDLE);
+        // next non-empty bucket of this workgroup, flows it holds in transit
+        if (tid < 64) {
+            unsigned best = 0xFFFFFFFFu, over = 0;
+            unsigned long long tr = 0;
+            for (unsigned j = tid; j + 1 < W; j += 64) {
+                const unsigned c = s_cnt[(unsigned)((t + 1 + j) & Wm)];
+                tr += c;
+                if (c > S) over = 1;
+                if (c && best == 0xFFFFFFFFu) best = j + 1;
             }
-            unsigned slot;
-            if (wave_append(&ctl->qcount[npar], imp, slot)) {
-                nqueue[slot] = P;
-                ++cU;
-                if (p.B[P]) {
-                    const unsigned s = atomicAdd(&ctl->bhit, 1u);
-                    p.bhitv[s] = P;
+            for (int o = 32; o > 0; o >>= 1) {
+                best = min(best, (unsigned)__shfl_xor(best, o));
+                tr += __shfl_xor(tr, o);
+                over |= __shfl_xor(over, o);
+            }
+            if (tid == 0) {
+                const unsigned fl = (s_flags & SF_OVER) | (over ? SF_OVER : 0u);
+                st_rlx(&ctl->nslot[g], (best == 0xFFFFFFFFu ? 0u : best) | fl);
+                st_rlx(&ctl->tslot[g], (unsigned)min(tr, 0xFFFFFFFFull));
+            }
+        }
+        if (!grid_sync(ctl, epoch, p.wait_limit)) { status = ST_BROKEN; break; }
+
+        // ---- Step 1 (Algorithm 4): next delivery time = earliest bucket anywhere.
+        {
+            const unsigned raw = tid < G ? ld_rlx(&ctl->nslot[tid]) : 0u;
+            if (tid == 0) { s_min = 0xFFFFFFFFu; s_flags = 0; }
+            __syncthreads();
+            const unsigned d0 = raw & SF_MASK;
+            if (tid < G && d0) atomicMin(&s_min, d0);
+            if (tid < G && (raw & SF_OVER)) atomicOr(&s_flags, SF_OVER);
+            if (lead && tid < G) {
+                const unsigned tr = ld_rlx(&ctl->tslot[tid]);
+                atomicAdd(&s_red[3], (unsigned long long)tr);   // s_red[3] zeroed below
+            }
+            __syncthreads();
+        }
+        const unsigned dmin = s_min;
+        const bool over = (s_flags & SF_OVER) != 0;
+        if (lead && tid == 0) {
+            cP = s_red[3] > cP ? s_red[3] : cP;
+            s_red[3] = 0;
+        }
+        __syncthreads();
+        if (over) { status = ST_OVERFLOW; break; }
+        if (dmin == 0xFFFFFFFFu) { status = ST_DONE; break; }            // condition 2
+        if (p.max_cycles > 0 && (long long)cyc >= p.max_cycles) { status = ST_CANCELED; break; }
+        t += dmin;
+        ++cyc;
+        if (lead && tid == 0) ++cC;
+
+        // ---- Arrival (Steps 1-3 and 8, Algorithms 4-6, 10): own segment of bucket t.
+        b_cur = (unsigned)(t & Wm);
+        bucket_n = s_cnt[b_cur];
+        if (tid == 0) s_qn = 0;
+        __syncthreads();
+        {
+            const uint2 *seg = p.pool + ((unsigned long long)b_cur * G + g) * S;
+            for (unsigned j = tid; j < bucket_n; j += BLOCK) {
+                const uint2 f = seg[j];
+                const unsigned P = f.x, q = f.y >> 3;
+                bool imp = false;
+                unsigned inb = 0;
+                if (q > (p.lab[P] >> 2)) {
+                    const unsigned old = atomicMax(&p.lab[P], q << 2);
+                    imp = (q > (old >> 2)) && (old & IDLE);
+                    inb = old & INB;
+                }
+                const unsigned long long m = __ballot(imp);
+                if (m) {
+                    const int ld = __ffsll((long long)m) - 1;
+                    unsigned base = 0;
+                    if ((int)lane == ld) base = atomicAdd(&s_qn, (unsigned)__popcll(m));
+                    base = __shfl(base, ld);
+                    if (imp) {
+                        const unsigned slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+                        if (slot < QS) myq[slot] = P | (inb ? QB_INB : 0u);
+                        else atomicOr(&s_flags, SF_OVER);
+                        if (inb) atomicOr(&s_flags, SF_BHIT);
+                        ++cU;
+                    }
                 }
             }
         }
-        if (lead_block && tid == 0) cR += nb;
-        b_last = b;
-        nb_last = nb;
-        if (!grid_barrier(ctl, gen, p.wait_limit)) { status = ST_BROKEN; break; }
-        if (lead_block && tid == 0) {
-            const unsigned nI = ld_acq(&ctl->qcount[npar]);
-            cI = nI > cI ? nI : cI;
+        if (tid == 0) cR += bucket_n;
+        __syncthreads();
+        if (tid == 0) {
+            s_cnt[b_cur] = 0;
+            st_rlx(&ctl->qslot[g], min(s_qn, QS) | (s_flags & (SF_OVER | SF_BHIT)));
+            s_flags = 0;
         }
+        if (!grid_sync(ctl, epoch, p.wait_limit)) { status = ST_BROKEN; break; }
+        unsigned fl;
+        Qtot = gather_frontier(fl);
+        if (lead && tid == 0) cI = Qtot > cI ? Qtot : cI;
+        if (fl & SF_OVER) { status = ST_OVERFLOW; break; }
 
         // ---- Step 6 (Algorithm 2): a vertex of B improved -> T = t.
-        const unsigned nbh = ld_acq(&ctl->bhit);
-        if (nbh) {
-            for (unsigned long long i = gtid; i < nbh; i += gsize) {
-                const unsigned P = p.bhitv[i];
-                const unsigned long long key =
-                    ((unsigned long long)(p.lab[P] >> 1) << 32) | (0xFFFFFFFFull - P);
-                atomicMax(&ctl->xkey, key);
+        if (fl & SF_BHIT) {
+            // X = best label among improved B vertices, smallest index on ties
+            {
+                const unsigned nq = min(s_qn, QS);
+                unsigned long long best = 0;
+                for (unsigned j = tid; j < nq; j += BLOCK) {
+                    const unsigned e = myq[j];
+                    if (e & QB_INB) {
+                        const unsigned P = e & ~QB_INB;
+                        const unsigned long long key =
+                            ((unsigned long long)(p.lab[P] >> 2) << 32) | (0xFFFFFFFFull - P);
+                        best = key > best ? key : best;
+                    }
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    const unsigned long long ob = __shfl_xor(best, o);
+                    best = ob > best ? ob : best;
+                }
+                if (tid == 0) s_red[0] = 0;
+                __syncthreads();
+                if (lane == 0 && best) atomicMax(&s_red[0], best);
+                __syncthreads();
+                if (tid == 0 && s_red[0]) atomicMax(&ctl->xkey, s_red[0]);
             }
-            if (!grid_barrier(ctl, gen, p.wait_limit)) { status = ST_BROKEN; break; }
-            const unsigned long long xk = ld_acq64(&ctl->xkey);
+            if (!grid_sync(ctl, epoch, p.wait_limit)) { status = ST_BROKEN; break; }
+            const unsigned long long xk = __hip_atomic_load(&ctl->xkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned X = (unsigned)(0xFFFFFFFFull - (xk & 0xFFFFFFFFull));
             const unsigned LX = (unsigned)(xk >> 32);
-            for (unsigned long long j = gtid; j < nb_last; j += gsize) {
-                const uint2 f = bk[j];
-                if (f.x == X && (f.y >> 3) == LX) atomicMin(&ctl->ydir, f.y & 7u);
+            // x = the delivery to X at T carrying LX, smallest sender
+            {
+                const uint2 *seg = p.pool + ((unsigned long long)b_cur * G + g) * S;
+                for (unsigned j = tid; j < bucket_n; j += BLOCK) {
+                    const uint2 f = seg[j];
+                    if (f.x == X && (f.y >> 3) == LX) atomicMin(&ctl->ydir, f.y & 7u);
+                }
             }
-            if (!grid_barrier(ctl, gen, p.wait_limit)) { status = ST_BROKEN; break; }
-            if (lead_block && tid == 0) {
-                const unsigned yd = ld_acq(&ctl->ydir);
+            if (!grid_sync(ctl, epoch, p.wait_limit)) { status = ST_BROKEN; break; }
+            if (lead && tid == 0) {
+                const unsigned yd = ld_rlx(&ctl->ydir);
+                const long long Y = (long long)X + p.off[yd];
                 const bool lower = (int)yd < D;
                 const int k = lower ? D - 1 - (int)yd : (int)yd - D;
-                const long long Y = lower ? (long long)X - p.stride[k] : (long long)X + p.stride[k];
                 ctl->res[0] = t;
                 ctl->res[1] = X;
                 ctl->res[2] = (long long)k * N + (lower ? Y : (long long)X);
@@ -437,45 +622,47 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
             break;
         }
     }
-    (void)b_last;
 
     // ---- outputs
     if (status == ST_DONE && p.labels_out) {
-        for (unsigned long long v = gtid; v < (unsigned long long)N; v += gsize)
-            p.labels_out[v] = p.lab[v] >> 1;
+        const long long chunk = (N + G - 1) / G;
+        const long long lo = (long long)g * chunk, hi = min(N, lo + chunk);
+        for (long long v = lo + tid; v < hi; v += BLOCK) p.labels_out[v] = p.lab[v] >> 2;
     }
+    __syncthreads();
     if (tid == 0) {
         s_red[0] = 0;
         s_red[1] = 0;
         s_red[2] = 0;
+        s_red[3] = 0;
     }
     __syncthreads();
     if (cU) atomicAdd(&s_red[0], cU);
     if (cD) atomicAdd(&s_red[1], cD);
     if (cE) atomicAdd(&s_red[2], cE);
+    if (cR) atomicAdd(&s_red[3], cR);
     __syncthreads();
     if (tid == 0) {
         if (s_red[0]) atomicAdd(&ctl->ctr[1], s_red[0]);
         if (s_red[1]) atomicAdd(&ctl->ctr[2], s_red[1]);
         if (s_red[2]) atomicAdd(&ctl->ctr[3], s_red[2]);
-        if (lead_block) {
+        if (s_red[3]) atomicAdd(&ctl->ctr[4], s_red[3]);
+        if (lead) {
             ctl->ctr[0] = cC;
-            ctl->ctr[4] = cR;
             ctl->ctr[5] = cP;
             ctl->ctr[6] = cI;
-            ctl->status = ld_acq((const unsigned *)&ctl->broken) ? ST_BROKEN : status;
-            if (status == ST_DONE && ld_acq(&ctl->bhit) == 0) {
-                ctl->res[0] = -1;
-                ctl->res[1] = -1;
-                ctl->res[2] = -1;
-                ctl->res[3] = -1;
-                ctl->res[4] = -1;
+            const int br = __hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ctl->status = br ? ST_BROKEN : status;
+            if (status == ST_DONE && ctl->xkey == 0) {
+                for (int i = 0; i < 5; ++i) ctl->res[i] = -1;
             }
         }
     }
 }
 
 __global__ void k_set_byte(uint8_t *p, long long i, uint8_t v) { p[i] = v; }
+
+size_t rec_bytes(int d) { return d == 1 ? 4 : (d == 2 ? 8 : 16); }
 
 }  // namespace
 
@@ -489,14 +676,15 @@ struct csp_ctx {
     int max_blocks[5] = {0, 0, 0, 0, 0};
     unsigned long long wall_khz = 100000;
     unsigned *lab = nullptr;
-    unsigned *q0 = nullptr, *q1 = nullptr, *bhit = nullptr;
-    size_t n_cap = 0;
+    size_t lab_cap = 0;
+    uint8_t *rec = nullptr;
+    size_t rec_cap = 0;
+    unsigned *queue = nullptr;
+    size_t queue_cap = 0;
     uint2 *pool = nullptr;
     size_t pool_cap = 0;            // flows
     Ctl *ctl = nullptr;
-    Info *info = nullptr;
     Ctl *h_ctl = nullptr;           // pinned
-    Info *h_info = nullptr;         // pinned
     uint8_t *in_buf = nullptr;      // staging for host-pointer solves
     size_t in_cap = 0;
     uint8_t *h_byte = nullptr;      // pinned scratch
@@ -520,9 +708,9 @@ int fail(csp_ctx *ctx, int code, const char *what, hipError_t e = hipSuccess)
     return code;
 }
 
-#define HIP_TRY(call, what)                                  \
-    do {                                                     \
-        hipError_t e_ = (call);                              \
+#define HIP_TRY(call, what)                                            \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
         if (e_ != hipSuccess) return fail(ctx, CSP_EDEVICE, what, e_); \
     } while (0)
 
@@ -536,23 +724,6 @@ int grow(csp_ctx *ctx, T **p, size_t &cap, size_t need, const char *what)
     hipError_t e = hipMalloc((void **)p, need * sizeof(T));
     if (e != hipSuccess) return fail(ctx, CSP_ENOMEM, what, e);
     cap = need;
-    return CSP_OK;
-}
-
-int ensure_vertex_buffers(csp_ctx *ctx, size_t N)
-{
-    if (N <= ctx->n_cap && ctx->lab) return CSP_OK;
-    for (unsigned **b : {&ctx->lab, &ctx->q0, &ctx->q1, &ctx->bhit}) {
-        if (*b) (void)hipFree(*b);
-        *b = nullptr;
-    }
-    ctx->n_cap = 0;
-    const size_t want = std::max<size_t>(N, 4096);
-    for (unsigned **b : {&ctx->lab, &ctx->q0, &ctx->q1, &ctx->bhit}) {
-        hipError_t e = hipMalloc((void **)b, want * sizeof(unsigned));
-        if (e != hipSuccess) return fail(ctx, CSP_ENOMEM, "vertex buffers", e);
-    }
-    ctx->n_cap = want;
     return CSP_OK;
 }
 
@@ -584,12 +755,23 @@ int check_shape(csp_ctx *ctx, int d, int64_t n, uint32_t M, long long &N)
 int blocks_for(csp_ctx *ctx, int d, long long N)
 {
     if (ctx->blocks_override > 0) return std::min(ctx->blocks_override, ctx->max_blocks[d]);
-    // Few vertices: one block (its barrier is a block barrier).  Otherwise
-    // about one block per 8K vertices, up to the co-resident limit.
+    // Few vertices: one workgroup (its barrier is a workgroup barrier).
+    // Otherwise about one workgroup per 8K vertices, up to one per CU.
     long long want = (N + 8191) / 8192;
-    if (N <= 16384) want = 1;
-    long long mx = (long long)ctx->max_blocks[d];
-    return (int)std::max(1ll, std::min(want, mx));
+    if (N <= 32768) want = 1;
+    return (int)std::max(1ll, std::min(want, (long long)ctx->max_blocks[d]));
+}
+
+void launch_pack(int d, long long n, long long N, const uint8_t *f1, const uint8_t *f2, void *rec, Ctl *ctl,
+                 int num_cu, hipStream_t s)
+{
+    const int nb = (int)std::max(1ll, std::min((N + 255) / 256, (long long)num_cu * 16));
+    switch (d) {
+    case 1: hipLaunchKernelGGL(k_pack<1>, dim3(nb), dim3(256), 0, s, n, N, f1, f2, (Rec<1>::T *)rec, ctl); break;
+    case 2: hipLaunchKernelGGL(k_pack<2>, dim3(nb), dim3(256), 0, s, n, N, f1, f2, (Rec<2>::T *)rec, ctl); break;
+    case 3: hipLaunchKernelGGL(k_pack<3>, dim3(nb), dim3(256), 0, s, n, N, f1, f2, (Rec<3>::T *)rec, ctl); break;
+    default: hipLaunchKernelGGL(k_pack<4>, dim3(nb), dim3(256), 0, s, n, N, f1, f2, (Rec<4>::T *)rec, ctl); break;
+    }
 }
 
 }  // namespace
@@ -617,14 +799,11 @@ int csp_create(int device, csp_ctx **out)
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel(d), BLOCK, 0) != hipSuccess || nb < 1)
             nb = 1;
-        nb = std::min(nb, 2);
-        ctx->max_blocks[d] = nb * ctx->num_cu;
+        ctx->max_blocks[d] = std::min(GMAX, std::min(nb, 1) * ctx->num_cu);
     }
     if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
         hipMalloc((void **)&ctx->ctl, sizeof(Ctl)) != hipSuccess ||
-        hipMalloc((void **)&ctx->info, sizeof(Info)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->h_info, sizeof(Info), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_byte, 64, hipHostMallocDefault) != hipSuccess) {
         csp_destroy(ctx);
         return CSP_ENOMEM;
@@ -637,10 +816,10 @@ void csp_destroy(csp_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    for (void *p : {(void *)ctx->lab, (void *)ctx->q0, (void *)ctx->q1, (void *)ctx->bhit,
-                    (void *)ctx->pool, (void *)ctx->ctl, (void *)ctx->info, (void *)ctx->in_buf})
+    for (void *p : {(void *)ctx->lab, (void *)ctx->rec, (void *)ctx->queue, (void *)ctx->pool,
+                    (void *)ctx->ctl, (void *)ctx->in_buf})
         if (p) (void)hipFree(p);
-    for (void *p : {(void *)ctx->h_ctl, (void *)ctx->h_info, (void *)ctx->h_byte})
+    for (void *p : {(void *)ctx->h_ctl, (void *)ctx->h_byte})
         if (p) (void)hipHostFree(p);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -663,74 +842,64 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
 
-    // validate and size the wheel
-    hipLaunchKernelGGL(k_zero_info, dim3(1), dim3(1), 0, s, ctx->info);
-    {
-        const long long work = (long long)d * N;
-        const int vb = (int)std::max(1ll, std::min((work + BLOCK - 1) / BLOCK, (long long)ctx->num_cu * 8));
-        hipLaunchKernelGGL(k_validate, dim3(vb), dim3(BLOCK), 0, s, d, (long long)n, N, f1, f2, A, B,
-                           ctx->info);
-    }
-    HIP_TRY(hipGetLastError(), "validate launch");
-    HIP_TRY(hipMemcpyAsync(ctx->h_info, ctx->info, sizeof(Info), hipMemcpyDeviceToHost, s), "info copy");
-    HIP_TRY(hipStreamSynchronize(s), "validate");
-    const Info info = *ctx->h_info;
-    if (info.bad & 1u) return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0");
-    if (info.bad & 2u) return fail(ctx, CSP_EINVAL, "A and B overlap");
-    unsigned W = 2;
-    while (W <= info.maxf1) W <<= 1;
-
-    rc = ensure_vertex_buffers(ctx, (size_t)N);
+    const int G = blocks_for(ctx, d, N);
+    rc = grow(ctx, &ctx->lab, ctx->lab_cap, (size_t)N, "labels");
+    if (rc) return rc;
+    rc = grow(ctx, &ctx->rec, ctx->rec_cap, (size_t)N * rec_bytes(d), "edge records");
     if (rc) return rc;
 
-    // bucket capacity: start at 2 * (directed edges) / W flows per bucket
-    unsigned long long cap = ctx->pool_hint ? ctx->pool_hint
-                                            : std::max<unsigned long long>(65536ull, (4ull * d * N) / W);
-    const int G = blocks_for(ctx, d, N);
-    // A bucket holds at most one flow per directed edge, so a capacity of
-    // 2dN cannot overflow; doubling up to it always ends.
-    const unsigned long long cap_max = std::max<unsigned long long>(2ull * d * N, 64ull);
-    cap = std::min(std::max<unsigned long long>(cap, 1ull), cap_max);
+    // wheel: start at 4 flows per directed edge spread over buckets and
+    // workgroups; frontier: at least the initial chunk of A per workgroup
+    unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G
+                                             : std::max<unsigned long long>(1ull << 20, 8ull * d * N);
+    const unsigned long long pool_max = 2ull * d * N * 256ull * G + (1ull << 20);
+    unsigned long long qs = std::max<unsigned long long>((N + G - 1) / G, 4096ull);
+
     for (;;) {
-        rc = grow(ctx, &ctx->pool, ctx->pool_cap, (size_t)(cap * W), "transit pool");
+        rc = grow(ctx, &ctx->pool, ctx->pool_cap, (size_t)pool, "transit pool");
+        if (rc) return rc;
+        rc = grow(ctx, &ctx->queue, ctx->queue_cap, (size_t)(qs * G), "frontier");
         if (rc) return rc;
         Params p;
         memset(&p, 0, sizeof(p));
-        p.n = n;
         p.N = N;
-        long long st = 1;
-        for (int k = 0; k < 4; ++k) {
-            p.stride[k] = st;
-            if (k < d) st *= n;
+        long long stride[4] = {1, 1, 1, 1};
+        for (int k = 1; k < d; ++k) stride[k] = stride[k - 1] * n;
+        for (int dir = 0; dir < 2 * d; ++dir) {
+            const bool lower = dir < d;
+            const int k = lower ? d - 1 - dir : dir - d;
+            p.off[dir] = lower ? -stride[k] : stride[k];
         }
-        p.f1 = f1;
-        p.f2 = f2;
+        p.rec = ctx->rec;
         p.A = A;
         p.B = B;
         p.M = M;
-        p.W = W;
-        p.cap = cap;
+        p.qs = (unsigned)qs;
+        p.pool_flows = pool;
         p.lab = ctx->lab;
-        p.queue0 = ctx->q0;
-        p.queue1 = ctx->q1;
-        p.bhitv = ctx->bhit;
+        p.queue = ctx->queue;
         p.pool = ctx->pool;
         p.ctl = ctx->ctl;
         p.labels_out = labels;
         p.max_cycles = max_cycles;
-        p.wait_limit = ctx->wall_khz * 1000ull * 20ull;    // 20 s
+        p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
         hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(BLOCK), 0, s, ctx->ctl);
+        launch_pack(d, n, N, f1, f2, ctx->rec, ctx->ctl, ctx->num_cu, s);
+        HIP_TRY(hipGetLastError(), "pack launch");
         void *args[] = {&p};
         HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
-        HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(d), dim3(G), dim3(BLOCK), args, 0, s),
-                "solve launch");
+        HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(d), dim3(G), dim3(BLOCK), args, 0, s), "solve launch");
         HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
         HIP_TRY(hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "ctl copy");
         HIP_TRY(hipStreamSynchronize(s), "solve");
         const Ctl &c = *ctx->h_ctl;
+        if (c.status == ST_INVAL || c.bad) {
+            return fail(ctx, CSP_EINVAL, c.bad ? "an edge has f1 or f2 equal to 0" : "A and B overlap");
+        }
         if (c.status == ST_OVERFLOW) {
-            if (cap >= cap_max) return fail(ctx, CSP_EOVERFLOW, "transit pool overflow at the edge bound");
-            cap = std::min(cap * 2, cap_max);
+            if (pool >= pool_max) return fail(ctx, CSP_EOVERFLOW, "transit pool overflow at the edge bound");
+            pool = std::min(pool * 2, pool_max);
+            qs = std::min<unsigned long long>(qs * 2, (unsigned long long)N);
             continue;
         }
         if (c.status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
