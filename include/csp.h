@@ -130,6 +130,14 @@ int csp_set_pool_hint(csp_ctx *ctx, uint64_t flows_per_bucket);
  * never results. */
 int csp_set_blocks(csp_ctx *ctx, int blocks);
 
+/* Phase timing of the cycle kernel (off by default).  When on, workgroup 0
+ * accumulates wall-clock time per phase; csp_last_phase_us fills us[6] with
+ * microseconds spent in: departure work, the barrier after it, finding the
+ * next time, arrival work, the barrier after it, and the frontier gather,
+ * for the last successful solve. */
+int csp_set_phase_timing(csp_ctx *ctx, int on);
+int csp_last_phase_us(const csp_ctx *ctx, double *us);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ CSP_MAX_M = 0x0FFFFFFF
 EXPORTED = (
     "csp_create", "csp_destroy", "csp_last_error", "csp_solve_dev", "csp_solve",
     "csp_reconstruct_dev", "csp_last_kernel_ms", "csp_set_pool_hint",
-    "csp_set_blocks",
+    "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us",
 )
 
 
@@ -70,6 +70,10 @@ def _load():
     lib.csp_set_pool_hint.restype = i32
     lib.csp_set_blocks.argtypes = [p, i32]
     lib.csp_set_blocks.restype = i32
+    lib.csp_set_phase_timing.argtypes = [p, i32]
+    lib.csp_set_phase_timing.restype = i32
+    lib.csp_last_phase_us.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
+    lib.csp_last_phase_us.restype = i32
     return lib
 
 
@@ -162,6 +166,20 @@ def csp_set_pool_hint(ctx, flows_per_bucket: int):
 
 def csp_set_blocks(ctx, blocks: int):
     _check(ctx, lib.csp_set_blocks(ctx, blocks))
+
+
+PHASES = ("departure", "barrier_after_departure", "next_time", "arrival",
+          "barrier_after_arrival", "frontier_gather")
+
+
+def csp_set_phase_timing(ctx, on: bool):
+    _check(ctx, lib.csp_set_phase_timing(ctx, 1 if on else 0))
+
+
+def csp_last_phase_us(ctx) -> dict:
+    us = (ctypes.c_double * 6)()
+    _check(ctx, lib.csp_last_phase_us(ctx, us))
+    return dict(zip(PHASES, list(us)))
 
 
 # --- convenience ------------------------------------------------------------

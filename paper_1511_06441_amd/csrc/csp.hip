@@ -91,6 +91,7 @@ struct Ctl {
     unsigned pad0;
     unsigned long long ctr[8];     // C U D E R P I
     long long res[5];              // T X x Y F2
+    unsigned long long prof[8];    // wall-clock ticks per phase (workgroup 0)
     int status;
     int broken;
 };
@@ -112,6 +113,7 @@ struct Params {
     unsigned *labels_out;
     long long max_cycles;
     unsigned long long wait_limit; // wall-clock ticks a barrier wait may take
+    int prof;                      // record per-phase time of workgroup 0
 };
 
 // record type per dimension: 2d (f1, f2) byte pairs
@@ -351,6 +353,18 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
 
     unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread
     unsigned long long cC = 0, cP = 0, cI = 0;              // lead workgroup, thread 0
+    // phase clock of workgroup 0: departure, departure barrier, next time,
+    // arrival, arrival barrier, frontier gather
+    unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
+    const bool timing = p.prof && lead && tid == 0;
+#define PHASE(k)                                         \
+    do {                                                 \
+        if (timing) {                                    \
+            const unsigned long long now_ = wall_clock64(); \
+            ph[k] += now_ - ph_t;                        \
+            ph_t = now_;                                 \
+        }                                                \
+    } while (0)
 
     for (unsigned i = tid; i < MAXW; i += BLOCK) s_cnt[i] = 0;
     if (tid == 0) {
@@ -422,6 +436,7 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
         cU += (g == 0 && tid == 0) ? Qtot : 0;
     }
 
+    if (timing) ph_t = wall_clock64();
     while (status == ST_RUNNING) {
         // ---- Departure (Steps 4-5, Algorithms 7-8): an equal slice of I_t.
         {
@@ -493,7 +508,9 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
                 st_rlx(&ctl->tslot[g], (unsigned)min(tr, 0xFFFFFFFFull));
             }
         }
+        PHASE(0);
         if (!grid_sync(ctl, epoch, p.wait_limit)) { status = ST_BROKEN; break; }
+        PHASE(1);
 
         // ---- Step 1 (Algorithm 4): next delivery time = earliest bucket anywhere.
         {
@@ -522,6 +539,7 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
         t += dmin;
         ++cyc;
         if (lead && tid == 0) ++cC;
+        PHASE(2);
 
         // ---- Arrival (Steps 1-3 and 8, Algorithms 4-6, 10): own segment of bucket t.
         b_cur = (unsigned)(t & Wm);
@@ -563,9 +581,12 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
             st_rlx(&ctl->qslot[g], min(s_qn, QS) | (s_flags & (SF_OVER | SF_BHIT)));
             s_flags = 0;
         }
+        PHASE(3);
         if (!grid_sync(ctl, epoch, p.wait_limit)) { status = ST_BROKEN; break; }
+        PHASE(4);
         unsigned fl;
         Qtot = gather_frontier(fl);
+        PHASE(5);
         if (lead && tid == 0) cI = Qtot > cI ? Qtot : cI;
         if (fl & SF_OVER) { status = ST_OVERFLOW; break; }
 
@@ -648,6 +669,7 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
         if (s_red[2]) atomicAdd(&ctl->ctr[3], s_red[2]);
         if (s_red[3]) atomicAdd(&ctl->ctr[4], s_red[3]);
         if (lead) {
+            for (int i = 0; i < 6; ++i) ctl->prof[i] = ph[i];
             ctl->ctr[0] = cC;
             ctl->ctr[5] = cP;
             ctl->ctr[6] = cI;
@@ -690,6 +712,8 @@ struct csp_ctx {
     uint8_t *h_byte = nullptr;      // pinned scratch
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_ms = -1.f;
+    unsigned long long last_prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int prof = 0;
     unsigned long long pool_hint = 0;
     int blocks_override = 0;
     char err[256] = {0};
@@ -883,6 +907,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         p.labels_out = labels;
         p.max_cycles = max_cycles;
         p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+        p.prof = ctx->prof;
         hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(BLOCK), 0, s, ctx->ctl);
         launch_pack(d, n, N, f1, f2, ctx->rec, ctx->ctl, ctx->num_cu, s);
         HIP_TRY(hipGetLastError(), "pack launch");
@@ -906,6 +931,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         if (c.status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out");
         if (c.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "solve did not finish");
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
+        for (int i = 0; i < 8; ++i) ctx->last_prof[i] = c.prof[i];
         out->T = c.res[0];
         out->X = c.res[1];
         out->x = c.res[2];
@@ -1008,6 +1034,20 @@ int csp_set_pool_hint(csp_ctx *ctx, uint64_t flows_per_bucket)
 {
     if (!ctx) return CSP_EINVAL;
     ctx->pool_hint = flows_per_bucket;
+    return CSP_OK;
+}
+
+int csp_set_phase_timing(csp_ctx *ctx, int on)
+{
+    if (!ctx) return CSP_EINVAL;
+    ctx->prof = on ? 1 : 0;
+    return CSP_OK;
+}
+
+int csp_last_phase_us(const csp_ctx *ctx, double *us)
+{
+    if (!ctx || !us) return CSP_EINVAL;
+    for (int i = 0; i < 6; ++i) us[i] = (double)ctx->last_prof[i] * 1000.0 / (double)ctx->wall_khz;
     return CSP_OK;
 }
 
