@@ -130,6 +130,13 @@ int csp_set_pool_hint(csp_ctx *ctx, uint64_t flows_per_bucket);
  * never results. */
 int csp_set_blocks(csp_ctx *ctx, int blocks);
 
+/* Kernel choice for later solves on ctx: 0 = automatic, 1 = range-owned
+ * (each workgroup keeps its range's labels in LDS; CSP_EINVAL when a range
+ * cannot fit), 2 = global labels.  Changes speed, never results.
+ * csp_last_path returns the kernel (1 or 2) the last solve used. */
+int csp_set_path(csp_ctx *ctx, int path);
+int csp_last_path(const csp_ctx *ctx);
+
 /* Phase timing of the cycle kernel (off by default).  When on, workgroup 0
  * accumulates wall-clock time per phase; csp_last_phase_us fills us[6] with
  * microseconds spent in: departure work, the barrier after it, finding the

@@ -25,7 +25,8 @@ CSP_MAX_M = 0x0FFFFFFF
 EXPORTED = (
     "csp_create", "csp_destroy", "csp_last_error", "csp_solve_dev", "csp_solve",
     "csp_reconstruct_dev", "csp_last_kernel_ms", "csp_set_pool_hint",
-    "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us",
+    "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us", "csp_set_path",
+    "csp_last_path",
 )
 
 
@@ -70,6 +71,10 @@ def _load():
     lib.csp_set_pool_hint.restype = i32
     lib.csp_set_blocks.argtypes = [p, i32]
     lib.csp_set_blocks.restype = i32
+    lib.csp_set_path.argtypes = [p, i32]
+    lib.csp_set_path.restype = i32
+    lib.csp_last_path.argtypes = [p]
+    lib.csp_last_path.restype = i32
     lib.csp_set_phase_timing.argtypes = [p, i32]
     lib.csp_set_phase_timing.restype = i32
     lib.csp_last_phase_us.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
@@ -166,6 +171,14 @@ def csp_set_pool_hint(ctx, flows_per_bucket: int):
 
 def csp_set_blocks(ctx, blocks: int):
     _check(ctx, lib.csp_set_blocks(ctx, blocks))
+
+
+def csp_set_path(ctx, path: int):
+    _check(ctx, lib.csp_set_path(ctx, path))
+
+
+def csp_last_path(ctx) -> int:
+    return lib.csp_last_path(ctx)
 
 
 PHASES = ("departure", "barrier_after_departure", "next_time", "arrival",

@@ -80,6 +80,13 @@ constexpr unsigned SF_MASK = 0x1FFFFFFFu;
 struct Ctl {
     unsigned grp[NGRP][32];        // barrier group counters, one per 128-byte line
     unsigned root[32];
+    // reducing barrier: per-group and root accumulators (min, or, sum)
+    unsigned gmin[NGRP][32];
+    unsigned gor[NGRP][32];
+    unsigned long long gsum[NGRP][16];
+    unsigned rmin[32];
+    unsigned ror[32];
+    unsigned long long rsum[16];
     unsigned flag[GMAX][32];       // per-workgroup release flags
     unsigned qslot[GMAX];          // arrival: frontier size | flags
     unsigned nslot[GMAX];          // departure: next delta (0 = none) | flags
@@ -258,6 +265,8 @@ __global__ void __launch_bounds__(BLOCK) k_reset_ctl(Ctl *ctl)
     for (unsigned i = threadIdx.x; i < sizeof(Ctl) / 4; i += BLOCK) w[i] = 0;
     __syncthreads();
     if (threadIdx.x == 0) ctl->ydir = 0xFFFFFFFFu;
+    if (threadIdx.x < NGRP) ctl->gmin[threadIdx.x][0] = 0xFFFFFFFFu;
+    if (threadIdx.x == 0) ctl->rmin[0] = 0xFFFFFFFFu;
 }
 
 // Repack SoA edge arrays into per-vertex records of 2d (f1, f2) pairs in
@@ -682,6 +691,552 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
     }
 }
 
+// ===========================================================================
+// Range-owned cycle kernel (labels in LDS)
+//
+// Workgroup r owns the contiguous vertex range [r*c, r*c + c).  It keeps the
+// range's labels, a frontier bitmap and a B bitmap in LDS and is the only
+// writer of those labels, so deliveries are LDS atomics.  A global mirror of
+// every label (written by the owner after each arrival phase) serves
+// neighbour tests across ranges.  Flows go to the outbox of the sending range
+// for (bucket, destination offset); the receiving range reads the outboxes of
+// the ranges within K of it, using fills the senders publish after each
+// departure phase.  Nothing on the wheel is a device atomic.  The grid
+// barrier also reduces the next event time, the flows in transit and flags.
+// ===========================================================================
+
+struct Red {
+    unsigned mn, orf;
+    unsigned long long sum;
+};
+
+// Counter-tree barrier (as grid_sync) that also combines one minimum, one
+// bitwise or and one sum over all workgroups.  The releaser writes the totals
+// into every workgroup's flag line before the new epoch, so each waiter reads
+// them from its own line.  track >= 0 folds the sum into ctl->ctr[track] by
+// maximum.  Arguments must be uniform across the calling workgroup.
+__device__ bool grid_reduce(Ctl *ctl, unsigned &epoch, unsigned long long limit, unsigned mn, unsigned orf,
+                            unsigned long long sum, int track, Red &out)
+{
+    __shared__ int s_ok;
+    __shared__ unsigned s_o[4];
+    __syncthreads();
+    ++epoch;
+    const unsigned G = gridDim.x;
+    if (G == 1) {
+        out.mn = mn;
+        out.orf = orf;
+        out.sum = sum;
+        if (track >= 0 && threadIdx.x == 0 && sum > ctl->ctr[track]) ctl->ctr[track] = sum;
+        return true;
+    }
+    if (threadIdx.x < 64) {
+        int releaser = 0;
+        unsigned rm = 0, ro = 0;
+        unsigned long long rs = 0;
+        if (threadIdx.x == 0) {
+            const unsigned grp = blockIdx.x % NGRP;
+            const unsigned ngrp = G < NGRP ? G : NGRP;
+            const unsigned members = (G - grp + NGRP - 1) / NGRP;
+            if (mn != 0xFFFFFFFFu) atomicMin(&ctl->gmin[grp][0], mn);
+            if (orf) atomicOr(&ctl->gor[grp][0], orf);
+            if (sum) atomicAdd(&ctl->gsum[grp][0], sum);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned a = __hip_atomic_fetch_add(&ctl->grp[grp][0], 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (a == members - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const unsigned gm = ld_rlx(&ctl->gmin[grp][0]);
+                const unsigned go = ld_rlx(&ctl->gor[grp][0]);
+                const unsigned long long gs =
+                    __hip_atomic_load(&ctl->gsum[grp][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st_rlx(&ctl->gmin[grp][0], 0xFFFFFFFFu);
+                st_rlx(&ctl->gor[grp][0], 0u);
+                __hip_atomic_store(&ctl->gsum[grp][0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st_rlx(&ctl->grp[grp][0], 0u);
+                if (gm != 0xFFFFFFFFu) atomicMin(&ctl->rmin[0], gm);
+                if (go) atomicOr(&ctl->ror[0], go);
+                if (gs) atomicAdd(&ctl->rsum[0], gs);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const unsigned rr = __hip_atomic_fetch_add(&ctl->root[0], 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                if (rr == ngrp - 1) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    rm = ld_rlx(&ctl->rmin[0]);
+                    ro = ld_rlx(&ctl->ror[0]);
+                    rs = __hip_atomic_load(&ctl->rsum[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    st_rlx(&ctl->rmin[0], 0xFFFFFFFFu);
+                    st_rlx(&ctl->ror[0], 0u);
+                    __hip_atomic_store(&ctl->rsum[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    st_rlx(&ctl->root[0], 0u);
+                    if (track >= 0) atomicMax(&ctl->ctr[track], rs);
+                    releaser = 1;
+                }
+            }
+        }
+        releaser = __shfl(releaser, 0);
+        if (releaser) {
+            rm = __shfl(rm, 0);
+            ro = __shfl(ro, 0);
+            const unsigned slo = __shfl((unsigned)rs, 0), shi = __shfl((unsigned)(rs >> 32), 0);
+            for (unsigned i = threadIdx.x; i < G; i += 64) {
+                st_rlx(&ctl->flag[i][1], rm);
+                st_rlx(&ctl->flag[i][2], ro);
+                st_rlx(&ctl->flag[i][3], slo);
+                st_rlx(&ctl->flag[i][4], shi);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (unsigned i = threadIdx.x; i < G; i += 64) st_rlx(&ctl->flag[i][0], epoch);
+        }
+        if (threadIdx.x == 0) {
+            int ok = 1;
+            const unsigned long long t0 = wall_clock64();
+            while (ld_rlx(&ctl->flag[blockIdx.x][0]) < epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - t0 > limit) {
+                    __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (__hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+            s_o[0] = ld_rlx(&ctl->flag[blockIdx.x][1]);
+            s_o[1] = ld_rlx(&ctl->flag[blockIdx.x][2]);
+            s_o[2] = ld_rlx(&ctl->flag[blockIdx.x][3]);
+            s_o[3] = ld_rlx(&ctl->flag[blockIdx.x][4]);
+            s_ok = ok;
+        }
+    }
+    __syncthreads();
+    out.mn = s_o[0];
+    out.orf = s_o[1];
+    out.sum = (unsigned long long)s_o[2] | ((unsigned long long)s_o[3] << 32);
+    const bool ok = s_ok != 0;
+    __syncthreads();
+    return ok;
+}
+
+constexpr int KMAX = 4;                 // largest range offset of a neighbour
+constexpr int NOMAX = 2 * KMAX + 1;
+
+struct P3 {
+    long long N;
+    long long off[8];              // neighbour offset per direction
+    long long offq[8];             // floor(off / c)
+    long long offr[8];             // off - c * floor(off / c), in [0, c)
+    long long c;                   // vertices per range
+    int K;                         // neighbours lie within K ranges
+    int xcd_map;                   // give each XCD a contiguous run of ranges
+    const void *rec;
+    const uint8_t *A, *B;
+    unsigned M;
+    unsigned *mirror;              // every label, written by its owner only
+    unsigned *lists;               // [G][c] frontier list per range
+    uint2 *pool;                   // [G][W][NO][S] outboxes
+    unsigned long long pool_flows;
+    unsigned *pub;                 // [G][MAXW][NO] published outbox fills
+    Ctl *ctl;
+    unsigned *labels_out;
+    long long max_cycles;
+    unsigned long long wait_limit;
+    int prof;
+};
+
+template <typename LT> __device__ __forceinline__ unsigned lab_get(const LT *lab, unsigned i) { return lab[i]; }
+
+// raise lab[i] to q; true when this call raised it
+__device__ __forceinline__ bool lab_raise(unsigned *lab, unsigned i, unsigned q)
+{
+    if (q <= lab[i]) return false;
+    return atomicMax(&lab[i], q) < q;
+}
+
+__device__ __forceinline__ bool lab_raise(uint16_t *lab, unsigned i, unsigned q)
+{
+    unsigned *w = reinterpret_cast<unsigned *>(lab) + (i >> 1);
+    const unsigned sh = (i & 1u) * 16u;
+    unsigned old = *w;
+    for (;;) {
+        const unsigned cur = (old >> sh) & 0xFFFFu;
+        if (q <= cur) return false;
+        const unsigned nw = (old & ~(0xFFFFu << sh)) | (q << sh);
+        const unsigned prev = atomicCAS(w, old, nw);
+        if (prev == old) return true;
+        old = prev;
+    }
+}
+
+template <int D, typename LT>
+__global__ void __launch_bounds__(BLOCK) k_solve_lds(P3 p)
+{
+    using RT = typename Rec<D>::T;
+    extern __shared__ unsigned smem[];
+    __shared__ unsigned s_wave[NWAVES];
+    __shared__ unsigned s_flags;
+    __shared__ unsigned s_min;
+    __shared__ unsigned long long s_sum;
+    __shared__ unsigned long long s_xkey;
+    __shared__ unsigned long long s_red[4];
+    __shared__ unsigned s_src[NOMAX];
+    __shared__ unsigned s_pre[NOMAX + 1];
+
+    Ctl *ctl = p.ctl;
+    const unsigned tid = threadIdx.x, lane = lane_id();
+    const unsigned G = gridDim.x;
+    const unsigned r = (p.xcd_map && (G % NGRP) == 0) ? (blockIdx.x % NGRP) * (G / NGRP) + blockIdx.x / NGRP
+                                                      : blockIdx.x;
+    const bool lead = blockIdx.x == 0;
+    const long long N = p.N, c = p.c;
+    const long long base = (long long)r * c;
+    const unsigned cr = (unsigned)max(0ll, min(c, N - base));
+    const int K = p.K, NO = 2 * K + 1;
+    const RT *rec = static_cast<const RT *>(p.rec);
+    unsigned epoch = 0;
+
+    unsigned W = 2;
+    while (W <= ctl->maxf1) W <<= 1;
+    const unsigned Wm = W - 1;
+    const unsigned long long S = p.pool_flows / ((unsigned long long)G * W * NO);
+
+    // LDS: labels | frontier bitmap | B bitmap | outbox fills [MAXW][NO] | dirty bits
+    const unsigned cw = (unsigned)((c + 31) / 32);
+    const unsigned lab_words = (unsigned)((c * (long long)sizeof(LT) + 3) / 4);
+    LT *lab = reinterpret_cast<LT *>(smem);
+    unsigned *fb = smem + lab_words;
+    unsigned *bb = fb + cw;
+    unsigned *cnt = bb + cw;
+    unsigned *dirty = cnt + MAXW * NO;
+    const unsigned ndirty = (MAXW * NO + 31) / 32;
+    unsigned *mylist = p.lists + (unsigned long long)r * c;
+    unsigned *mypub = p.pub + (unsigned long long)r * MAXW * NO;
+    auto outbox = [&](unsigned long long src, unsigned bk, unsigned oi) {
+        return p.pool + ((src * W + bk) * (unsigned long long)NO + oi) * S;
+    };
+
+    unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread
+    unsigned long long cC = 0;                              // lead workgroup, thread 0
+    unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
+    const bool timing = p.prof && lead && tid == 0;
+
+    for (unsigned i = tid; i < lab_words + 2 * cw + MAXW * NO + ndirty; i += BLOCK) smem[i] = 0;
+    for (unsigned i = tid; i < MAXW * NO; i += BLOCK) mypub[i] = 0;
+    if (tid == 0) {
+        s_flags = 0;
+        s_xkey = 0;
+        for (int i = 0; i < 4; ++i) s_red[i] = 0;
+    }
+    __syncthreads();
+
+    int status = ctl->bad ? ST_INVAL : ST_RUNNING;
+
+    // ---- Initialization (Algorithm 3): Label = M on A, 0 elsewhere; A is I_0.
+    if (status == ST_RUNNING) {
+        for (unsigned i = tid; i < cr; i += BLOCK) {
+            const long long v = base + i;
+            const bool a = p.A[v] != 0, b = p.B[v] != 0;
+            if (a && b) atomicOr(&s_flags, SF_INVAL);
+            if (a) {
+                lab[i] = (LT)p.M;
+                atomicOr(&fb[i >> 5], 1u << (i & 31));
+            }
+            if (b) atomicOr(&bb[i >> 5], 1u << (i & 31));
+            p.mirror[v] = a ? p.M : 0u;
+        }
+    }
+    __syncthreads();
+
+    // Frontier bitmap -> sorted list of local indices; publish improved labels
+    // to the mirror; clear the bitmap; best (label, -index) among B members.
+    auto compact = [&]() -> unsigned {
+        unsigned total = 0;
+        unsigned long long bestB = 0;
+        for (unsigned w0 = 0; w0 < cw; w0 += BLOCK) {
+            const unsigned wi = w0 + tid;
+            unsigned bits = 0, bm = 0;
+            if (wi < cw) {
+                bits = fb[wi];
+                bm = bits & bb[wi];
+                fb[wi] = 0;
+            }
+            unsigned tot;
+            const unsigned ex = block_scan((unsigned)__popc(bits), s_wave, &tot);
+            unsigned k = total + ex;
+            while (bits) {
+                const unsigned bt = (unsigned)(__ffs(bits) - 1);
+                bits &= bits - 1u;
+                const unsigned i = wi * 32u + bt;
+                mylist[k++] = i;
+                const unsigned L = lab_get(lab, i);
+                p.mirror[base + i] = L;
+                if ((bm >> bt) & 1u) {
+                    const unsigned long long key =
+                        ((unsigned long long)L << 32) | (0xFFFFFFFFull - (unsigned long long)(base + i));
+                    bestB = key > bestB ? key : bestB;
+                }
+            }
+            total += tot;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long ob = __shfl_xor(bestB, o);
+            bestB = ob > bestB ? ob : bestB;
+        }
+        if (lane == 0 && bestB) {
+            atomicMax(&s_xkey, bestB);
+            atomicOr(&s_flags, SF_BHIT);
+        }
+        __syncthreads();
+        return total;
+    };
+
+    unsigned nlist = 0;
+    Red red;
+    if (status == ST_RUNNING) {
+        nlist = compact();
+        if (tid == 0) cU += nlist;
+        const unsigned fl = s_flags;
+        if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, fl & SF_INVAL, 0, -1, red)) status = ST_BROKEN;
+        else if (red.orf & SF_INVAL) status = ST_INVAL;
+    }
+
+    long long t = 0;
+    unsigned cyc = 0;
+    unsigned b_cur = 0;
+    if (timing) ph_t = wall_clock64();
+#define PHASE3(k)                                            \
+    do {                                                     \
+        if (timing) {                                        \
+            const unsigned long long now_ = wall_clock64();  \
+            ph[k] += now_ - ph_t;                            \
+            ph_t = now_;                                     \
+        }                                                    \
+    } while (0)
+
+    while (status == ST_RUNNING) {
+        // ---- Departure (Steps 4-5, Algorithms 7-8) from I_t within this range.
+        {
+            // the bucket delivered at t is free again
+            const unsigned bt = (unsigned)(t & Wm);
+            if (tid < (unsigned)NO) {
+                const unsigned k = bt * NO + tid;
+                if (cnt[k]) {
+                    cnt[k] = 0;
+                    if ((int)tid != K) atomicOr(&dirty[k >> 5], 1u << (k & 31));
+                }
+            }
+            __syncthreads();
+            for (unsigned j = tid; j < nlist; j += BLOCK) {
+                const unsigned i = mylist[j];
+                const long long Q = base + i;
+                const unsigned L = lab_get(lab, i);
+                const RT rv = rec[Q];
+                unsigned lp[2 * D];
+                int oo[2 * D];
+#pragma unroll
+                for (int dir = 0; dir < 2 * D; ++dir) {
+                    unsigned a1, a2;
+                    rec_get<D>(rv, dir, a1, a2);
+                    oo[dir] = 0;
+                    lp[dir] = 0xFFFFFFFFu;
+                    if (a1) {
+                        const long long lo = (long long)i + p.offr[dir];
+                        const int o = (int)p.offq[dir] + (lo >= c ? 1 : 0);
+                        oo[dir] = o;
+                        lp[dir] = o == 0 ? lab_get(lab, (unsigned)(lo >= c ? lo - c : lo))
+                                         : p.mirror[Q + p.off[dir]];
+                    }
+                }
+#pragma unroll
+                for (int dir = 0; dir < 2 * D; ++dir) {
+                    unsigned a1, a2;
+                    rec_get<D>(rv, dir, a1, a2);
+                    if (a1) {
+                        ++cD;
+                        const int q = (int)L - (int)a2;
+                        if (q > (int)lp[dir]) {
+                            const unsigned bk = (unsigned)((t + a1) & Wm);
+                            const unsigned oi = (unsigned)(oo[dir] + K);
+                            const unsigned k = bk * NO + oi;
+                            const unsigned pos = atomicAdd(&cnt[k], 1u);
+                            if (pos < S) {
+                                // the receiver sees the sender in the opposite direction
+                                outbox(r, bk, oi)[pos] =
+                                    make_uint2((unsigned)(Q + p.off[dir]),
+                                               ((unsigned)q << 3) | (unsigned)(2 * D - 1 - dir));
+                            } else {
+                                atomicOr(&s_flags, SF_OVER);
+                            }
+                            if (oi != (unsigned)K) atomicOr(&dirty[k >> 5], 1u << (k & 31));
+                            ++cE;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // publish changed remote fills; next delivery time; flows in transit
+        {
+            for (unsigned wd = tid; wd < ndirty; wd += BLOCK) {
+                unsigned bits = dirty[wd];
+                if (bits) {
+                    dirty[wd] = 0;
+                    while (bits) {
+                        const unsigned bt = (unsigned)(__ffs(bits) - 1);
+                        bits &= bits - 1u;
+                        const unsigned k = wd * 32u + bt;
+                        st_rlx(&mypub[k], cnt[k]);
+                    }
+                }
+            }
+            if (tid == 0) {
+                s_min = 0xFFFFFFFFu;
+                s_sum = 0;
+            }
+            __syncthreads();
+            unsigned best = 0xFFFFFFFFu, over = 0;
+            unsigned long long tr = 0;
+            for (unsigned k = tid; k < W * (unsigned)NO; k += BLOCK) {
+                const unsigned v = cnt[k];
+                if (v) {
+                    const unsigned bk = k / (unsigned)NO;
+                    const unsigned delta = (unsigned)((bk - (unsigned)t) & Wm);
+                    best = delta < best ? delta : best;
+                    tr += v;
+                    if (v > S) over = 1;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                best = min(best, (unsigned)__shfl_xor(best, o));
+                tr += __shfl_xor(tr, o);
+                over |= __shfl_xor(over, o);
+            }
+            if (lane == 0) {
+                if (best != 0xFFFFFFFFu) atomicMin(&s_min, best);
+                if (tr) atomicAdd(&s_sum, tr);
+                if (over) atomicOr(&s_flags, SF_OVER);
+            }
+            __syncthreads();
+        }
+        PHASE3(0);
+        const unsigned my_min = s_min;
+        const unsigned my_fl = s_flags & SF_OVER;
+        const unsigned long long my_tr = s_sum;
+        if (!grid_reduce(ctl, epoch, p.wait_limit, my_min, my_fl, my_tr, 5, red)) { status = ST_BROKEN; break; }
+        PHASE3(1);
+
+        // ---- Step 1 (Algorithm 4): the earliest bucket anywhere.
+        if (red.orf & SF_OVER) { status = ST_OVERFLOW; break; }
+        if (red.mn == 0xFFFFFFFFu) { status = ST_DONE; break; }            // condition 2
+        if (p.max_cycles > 0 && (long long)cyc >= p.max_cycles) { status = ST_CANCELED; break; }
+        t += red.mn;
+        ++cyc;
+        if (lead && tid == 0) ++cC;
+        b_cur = (unsigned)(t & Wm);
+        if (tid == 0) s_flags = 0;
+        PHASE3(2);
+
+        // ---- Arrival (Steps 1-3 and 8, Algorithms 4-6, 10): flows for this range.
+        if (tid < (unsigned)NO) {
+            const int o = (int)tid - K;                   // sender range r + o
+            const long long src = (long long)r + o;
+            unsigned v = 0;
+            if (o == 0) v = cnt[b_cur * NO + K];
+            else if (src >= 0 && src < (long long)G)
+                v = ld_rlx(&p.pub[((unsigned long long)src * MAXW + b_cur) * NO + (unsigned)(K - o)]);
+            s_src[tid] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_pre[0] = 0;
+            for (int oi = 0; oi < NO; ++oi) s_pre[oi + 1] = s_pre[oi] + s_src[oi];
+        }
+        __syncthreads();
+        const unsigned *pre = s_pre;
+        const unsigned F = pre[NO];
+        for (unsigned j = tid; j < F; j += BLOCK) {
+            int oi = 0;
+            while (j >= pre[oi + 1]) ++oi;
+            const long long src = (long long)r + (oi - K);
+            const uint2 f = outbox((unsigned long long)src, b_cur, (unsigned)(2 * K - oi))[j - pre[oi]];
+            const unsigned i = (unsigned)((long long)f.x - base);
+            if (lab_raise(lab, i, f.y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
+        }
+        if (tid == 0) cR += F;
+        __syncthreads();
+        nlist = compact();
+        if (tid == 0) cU += nlist;
+        PHASE3(3);
+        const unsigned fl = s_flags & SF_BHIT;
+        if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, fl, nlist, 6, red)) { status = ST_BROKEN; break; }
+        PHASE3(4);
+
+        // ---- Step 6 (Algorithm 2): a vertex of B improved -> T = t.
+        if (red.orf & SF_BHIT) {
+            if (tid == 0 && s_xkey) atomicMax(&ctl->xkey, s_xkey);
+            if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, 0, 0, -1, red)) { status = ST_BROKEN; break; }
+            const unsigned long long xk =
+                __hip_atomic_load(&ctl->xkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned X = (unsigned)(0xFFFFFFFFull - (xk & 0xFFFFFFFFull));
+            const unsigned LX = (unsigned)(xk >> 32);
+            if ((long long)X >= base && (long long)X < base + (long long)cr) {
+                for (unsigned j = tid; j < F; j += BLOCK) {
+                    int oi = 0;
+                    while (j >= pre[oi + 1]) ++oi;
+                    const long long src = (long long)r + (oi - K);
+                    const uint2 f = outbox((unsigned long long)src, b_cur, (unsigned)(2 * K - oi))[j - pre[oi]];
+                    if (f.x == X && (f.y >> 3) == LX) atomicMin(&ctl->ydir, f.y & 7u);
+                }
+            }
+            if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, 0, 0, -1, red)) { status = ST_BROKEN; break; }
+            if (lead && tid == 0) {
+                const unsigned yd = ld_rlx(&ctl->ydir);
+                const long long Y = (long long)X + p.off[yd];
+                const bool lower = (int)yd < D;
+                const int k = lower ? D - 1 - (int)yd : (int)yd - D;
+                ctl->res[0] = t;
+                ctl->res[1] = X;
+                ctl->res[2] = (long long)k * N + (lower ? Y : (long long)X);
+                ctl->res[3] = Y;
+                ctl->res[4] = (long long)p.M - (long long)LX;
+            }
+            status = ST_DONE;
+            break;
+        }
+        PHASE3(5);
+    }
+#undef PHASE3
+
+    // ---- outputs
+    if (status == ST_DONE && p.labels_out) {
+        for (unsigned i = tid; i < cr; i += BLOCK) p.labels_out[base + i] = lab_get(lab, i);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = 0; i < 4; ++i) s_red[i] = 0;
+    }
+    __syncthreads();
+    if (cU) atomicAdd(&s_red[0], cU);
+    if (cD) atomicAdd(&s_red[1], cD);
+    if (cE) atomicAdd(&s_red[2], cE);
+    if (cR) atomicAdd(&s_red[3], cR);
+    __syncthreads();
+    if (tid == 0) {
+        if (s_red[0]) atomicAdd(&ctl->ctr[1], s_red[0]);
+        if (s_red[1]) atomicAdd(&ctl->ctr[2], s_red[1]);
+        if (s_red[2]) atomicAdd(&ctl->ctr[3], s_red[2]);
+        if (s_red[3]) atomicAdd(&ctl->ctr[4], s_red[3]);
+        if (lead) {
+            for (int i = 0; i < 6; ++i) ctl->prof[i] = ph[i];
+            ctl->ctr[0] = cC;
+            const int br = __hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ctl->status = br ? ST_BROKEN : status;
+            if (status == ST_DONE && ctl->xkey == 0) {
+                for (int i = 0; i < 5; ++i) ctl->res[i] = -1;
+            }
+        }
+    }
+}
+
 __global__ void k_set_byte(uint8_t *p, long long i, uint8_t v) { p[i] = v; }
 
 size_t rec_bytes(int d) { return d == 1 ? 4 : (d == 2 ? 8 : 16); }
@@ -716,6 +1271,12 @@ struct csp_ctx {
     int prof = 0;
     unsigned long long pool_hint = 0;
     int blocks_override = 0;
+    int path_override = 0;          // 0 auto, 1 LDS ranges, 2 global labels
+    int last_path = 0;
+    size_t lds_limit = 65536;
+    unsigned *pub = nullptr;
+    size_t pub_cap = 0;
+    unsigned long long pool_flows_seen = 0;   // largest pool a solve needed so far
     char err[256] = {0};
 };
 
@@ -750,6 +1311,46 @@ int grow(csp_ctx *ctx, T **p, size_t &cap, size_t need, const char *what)
     cap = need;
     return CSP_OK;
 }
+
+const void *lds_kernel(int d, int lt)
+{
+    if (lt == 2) {
+        switch (d) {
+        case 1: return (const void *)k_solve_lds<1, uint16_t>;
+        case 2: return (const void *)k_solve_lds<2, uint16_t>;
+        case 3: return (const void *)k_solve_lds<3, uint16_t>;
+        default: return (const void *)k_solve_lds<4, uint16_t>;
+        }
+    }
+    switch (d) {
+    case 1: return (const void *)k_solve_lds<1, unsigned>;
+    case 2: return (const void *)k_solve_lds<2, unsigned>;
+    case 3: return (const void *)k_solve_lds<3, unsigned>;
+    default: return (const void *)k_solve_lds<4, unsigned>;
+    }
+}
+
+// Layout of a range-owned solve: G ranges of c vertices, neighbours within K
+// ranges, LT-byte LDS labels, dynamic LDS bytes.
+struct LdsPlan {
+    bool ok = false;
+    int G = 1;
+    long long c = 0;
+    int K = 0;
+    int lt = 4;
+    size_t lds = 0;
+};
+
+size_t lds_bytes_for(long long c, int K, int lt)
+{
+    const long long cw = (c + 31) / 32;
+    const long long lab_words = (c * lt + 3) / 4;
+    const long long NO = 2 * K + 1;
+    const long long ndirty = (MAXW * NO + 31) / 32;
+    return (size_t)(4 * (lab_words + 2 * cw + MAXW * NO + ndirty));
+}
+
+LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M, int G_want);
 
 const void *solve_kernel(int d)
 {
@@ -786,6 +1387,35 @@ int blocks_for(csp_ctx *ctx, int d, long long N)
     return (int)std::max(1ll, std::min(want, (long long)ctx->max_blocks[d]));
 }
 
+LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M, int G_want)
+{
+    LdsPlan pl;
+    long long smax = 1;
+    for (int k = 1; k < d; ++k) smax *= n;           // largest neighbour offset
+    const size_t budget = ctx->lds_limit > 2048 ? ctx->lds_limit - 2048 : 0;   // static LDS margin
+    for (int G = std::max(1, G_want); G >= 1; G = (G > 1 ? G / 2 : 0)) {
+        const long long c = (N + G - 1) / G;
+        if ((long long)(G - 1) * c >= N) continue;    // empty range
+        const int K = G == 1 ? 0 : (int)((smax + c - 1) / c);
+        if (K > KMAX) continue;
+        for (int lt : {4, 2}) {
+            if (lt == 2 && M > 0xFFFFu) continue;
+            const size_t need = lds_bytes_for(c, K, lt);
+            if (need <= budget) {
+                pl.ok = true;
+                pl.G = G;
+                pl.c = c;
+                pl.K = K;
+                pl.lt = lt;
+                pl.lds = need;
+                return pl;
+            }
+        }
+        if (G == 1) break;
+    }
+    return pl;
+}
+
 void launch_pack(int d, long long n, long long N, const uint8_t *f1, const uint8_t *f2, void *rec, Ctl *ctl,
                  int num_cu, hipStream_t s)
 {
@@ -814,6 +1444,7 @@ int csp_create(int device, csp_ctx **out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return CSP_EDEVICE; }
     ctx->num_cu = prop.multiProcessorCount;
+    ctx->lds_limit = std::max<size_t>(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
     {
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
@@ -841,7 +1472,7 @@ void csp_destroy(csp_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     for (void *p : {(void *)ctx->lab, (void *)ctx->rec, (void *)ctx->queue, (void *)ctx->pool,
-                    (void *)ctx->ctl, (void *)ctx->in_buf})
+                    (void *)ctx->ctl, (void *)ctx->in_buf, (void *)ctx->pub})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)ctx->h_ctl, (void *)ctx->h_byte})
         if (p) (void)hipHostFree(p);
@@ -866,55 +1497,120 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
 
-    const int G = blocks_for(ctx, d, N);
     rc = grow(ctx, &ctx->lab, ctx->lab_cap, (size_t)N, "labels");
     if (rc) return rc;
     rc = grow(ctx, &ctx->rec, ctx->rec_cap, (size_t)N * rec_bytes(d), "edge records");
     if (rc) return rc;
 
-    // wheel: start at 4 flows per directed edge spread over buckets and
-    // workgroups; frontier: at least the initial chunk of A per workgroup
-    unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G
-                                             : std::max<unsigned long long>(1ull << 20, 8ull * d * N);
-    const unsigned long long pool_max = 2ull * d * N * 256ull * G + (1ull << 20);
+    long long stride[4] = {1, 1, 1, 1};
+    for (int k = 1; k < d; ++k) stride[k] = stride[k - 1] * n;
+    long long off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int dir = 0; dir < 2 * d; ++dir) {
+        const bool lower = dir < d;
+        const int k = lower ? d - 1 - dir : dir - d;
+        off[dir] = lower ? -stride[k] : stride[k];
+    }
+
+    // Range-owned kernel when a range fits in LDS, else the global-label kernel.
+    int G = blocks_for(ctx, d, N);
+    LdsPlan plan;
+    if (ctx->path_override != 2) {
+        plan = plan_lds(ctx, d, n, N, M, G);
+        if (plan.ok) {
+            const void *kf = lds_kernel(d, plan.lt);
+            if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds) != hipSuccess)
+                plan.ok = false;
+            int nb = 0;
+            if (plan.ok && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kf, BLOCK, plan.lds) != hipSuccess ||
+                            nb * ctx->num_cu < plan.G))
+                plan.ok = false;
+        }
+        if (!plan.ok && ctx->path_override == 1) return fail(ctx, CSP_EINVAL, "range does not fit in LDS");
+    }
+    const bool use_lds = plan.ok;
+    if (use_lds) G = plan.G;
+    ctx->last_path = use_lds ? 1 : 2;
+
+    // wheel capacity: start from the largest a solve has needed, at least
+    // 16 flows per directed-edge endpoint; doubled on overflow up to the
+    // bound at which no bucket can overflow
+    const unsigned long long NO = use_lds ? (unsigned long long)(2 * plan.K + 1) : 1ull;
+    unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G * NO
+                                             : std::max<unsigned long long>(
+                                                   std::max<unsigned long long>(1ull << 20, 16ull * d * N),
+                                                   ctx->pool_flows_seen);
+    const unsigned long long pool_max = 2ull * d * N * 256ull * G * NO + (1ull << 20);
     unsigned long long qs = std::max<unsigned long long>((N + G - 1) / G, 4096ull);
 
     for (;;) {
         rc = grow(ctx, &ctx->pool, ctx->pool_cap, (size_t)pool, "transit pool");
         if (rc) return rc;
-        rc = grow(ctx, &ctx->queue, ctx->queue_cap, (size_t)(qs * G), "frontier");
-        if (rc) return rc;
-        Params p;
-        memset(&p, 0, sizeof(p));
-        p.N = N;
-        long long stride[4] = {1, 1, 1, 1};
-        for (int k = 1; k < d; ++k) stride[k] = stride[k - 1] * n;
-        for (int dir = 0; dir < 2 * d; ++dir) {
-            const bool lower = dir < d;
-            const int k = lower ? d - 1 - dir : dir - d;
-            p.off[dir] = lower ? -stride[k] : stride[k];
-        }
-        p.rec = ctx->rec;
-        p.A = A;
-        p.B = B;
-        p.M = M;
-        p.qs = (unsigned)qs;
-        p.pool_flows = pool;
-        p.lab = ctx->lab;
-        p.queue = ctx->queue;
-        p.pool = ctx->pool;
-        p.ctl = ctx->ctl;
-        p.labels_out = labels;
-        p.max_cycles = max_cycles;
-        p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
-        p.prof = ctx->prof;
         hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(BLOCK), 0, s, ctx->ctl);
         launch_pack(d, n, N, f1, f2, ctx->rec, ctx->ctl, ctx->num_cu, s);
         HIP_TRY(hipGetLastError(), "pack launch");
-        void *args[] = {&p};
-        HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
-        HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(d), dim3(G), dim3(BLOCK), args, 0, s), "solve launch");
-        HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
+        if (use_lds) {
+            rc = grow(ctx, &ctx->queue, ctx->queue_cap, (size_t)(plan.c * G), "frontier");
+            if (rc) return rc;
+            rc = grow(ctx, &ctx->pub, ctx->pub_cap, (size_t)G * MAXW * NOMAX, "published fills");
+            if (rc) return rc;
+            P3 p;
+            memset(&p, 0, sizeof(p));
+            p.N = N;
+            p.c = plan.c;
+            for (int dir = 0; dir < 8; ++dir) {
+                p.off[dir] = off[dir];
+                long long q = off[dir] >= 0 ? off[dir] / plan.c : -((-off[dir] + plan.c - 1) / plan.c);
+                p.offq[dir] = q;
+                p.offr[dir] = off[dir] - q * plan.c;
+            }
+            p.K = plan.K;
+            p.xcd_map = 1;
+            p.rec = ctx->rec;
+            p.A = A;
+            p.B = B;
+            p.M = M;
+            p.mirror = ctx->lab;
+            p.lists = ctx->queue;
+            p.pool = ctx->pool;
+            p.pool_flows = pool;
+            p.pub = ctx->pub;
+            p.ctl = ctx->ctl;
+            p.labels_out = labels;
+            p.max_cycles = max_cycles;
+            p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+            p.prof = ctx->prof;
+            void *args[] = {&p};
+            HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
+            HIP_TRY(hipLaunchCooperativeKernel(lds_kernel(d, plan.lt), dim3(G), dim3(BLOCK), args,
+                                               (unsigned)plan.lds, s),
+                    "solve launch");
+            HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
+        } else {
+            rc = grow(ctx, &ctx->queue, ctx->queue_cap, (size_t)(qs * G), "frontier");
+            if (rc) return rc;
+            Params p;
+            memset(&p, 0, sizeof(p));
+            p.N = N;
+            for (int dir = 0; dir < 8; ++dir) p.off[dir] = off[dir];
+            p.rec = ctx->rec;
+            p.A = A;
+            p.B = B;
+            p.M = M;
+            p.qs = (unsigned)qs;
+            p.pool_flows = pool;
+            p.lab = ctx->lab;
+            p.queue = ctx->queue;
+            p.pool = ctx->pool;
+            p.ctl = ctx->ctl;
+            p.labels_out = labels;
+            p.max_cycles = max_cycles;
+            p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+            p.prof = ctx->prof;
+            void *args[] = {&p};
+            HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
+            HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(d), dim3(G), dim3(BLOCK), args, 0, s), "solve launch");
+            HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
+        }
         HIP_TRY(hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "ctl copy");
         HIP_TRY(hipStreamSynchronize(s), "solve");
         const Ctl &c = *ctx->h_ctl;
@@ -930,6 +1626,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         if (c.status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
         if (c.status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out");
         if (c.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "solve did not finish");
+        if (!ctx->pool_hint) ctx->pool_flows_seen = std::max(ctx->pool_flows_seen, pool);
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
         for (int i = 0; i < 8; ++i) ctx->last_prof[i] = c.prof[i];
         out->T = c.res[0];
@@ -1049,6 +1746,18 @@ int csp_last_phase_us(const csp_ctx *ctx, double *us)
     if (!ctx || !us) return CSP_EINVAL;
     for (int i = 0; i < 6; ++i) us[i] = (double)ctx->last_prof[i] * 1000.0 / (double)ctx->wall_khz;
     return CSP_OK;
+}
+
+int csp_set_path(csp_ctx *ctx, int path)
+{
+    if (!ctx || path < 0 || path > 2) return CSP_EINVAL;
+    ctx->path_override = path;
+    return CSP_OK;
+}
+
+int csp_last_path(const csp_ctx *ctx)
+{
+    return ctx ? ctx->last_path : CSP_EINVAL;
 }
 
 int csp_set_blocks(csp_ctx *ctx, int blocks)

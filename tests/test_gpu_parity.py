@@ -41,16 +41,24 @@ def solver(torch):
     s.close()
 
 
-def gpu_solve(solver, torch, inst, blocks=0, **kw):
+PATHS = [1, 2]          # range-owned (labels in LDS), global labels
+
+
+def gpu_solve(solver, torch, inst, blocks=0, path=0, **kw):
     from paper_1511_06441_amd import csp
     di = csp.to_device(inst)
     lab = torch.zeros(inst.N, dtype=torch.int32, device="cuda")
     csp.csp_set_blocks(solver.ctx, blocks)
+    csp.csp_set_path(solver.ctx, path)
     try:
         res, cnt = solver.solve(di, labels=lab, **kw)
+        used = csp.csp_last_path(solver.ctx)
     finally:
         csp.csp_set_blocks(solver.ctx, 0)
+        csp.csp_set_path(solver.ctx, 0)
     torch.cuda.synchronize()
+    _say("  path", used, "kernel_ms %.3f" % csp.csp_last_kernel_ms(solver.ctx))
+    assert path == 0 or used == path
     return res, cnt, lab.cpu().numpy().view(np.uint32)
 
 
@@ -100,20 +108,22 @@ SMALL = [
 ]
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("case", SMALL, ids=[f"d{c[0]}n{c[1]}s{c[2]}M{c[5]}" for c in SMALL])
-def test_small_vs_oracle(solver, torch, case):
+def test_small_vs_oracle(solver, torch, case, path):
     d, n, seed, K1, K2, M, c1, c2 = case
     inst = gen.opposite_faces(d, n, seed, K1, K2, M, f1_const=c1, f2_const=c2)
     inst.name = f"d{d}n{n}s{seed}M{M}"
-    _say("case", inst.name)
+    _say("case", inst.name, "path", path)
     ref = _oracle(inst)
-    res, cnt, lab = gpu_solve(solver, torch, inst)
+    res, cnt, lab = gpu_solve(solver, torch, inst, path=path)
     _compare(inst, res, cnt, lab, ref)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("blocks", [1, 2, 3, 8, 64, 256])
 @pytest.mark.parametrize("which", ["square", "cube", "corner"])
-def test_block_counts_vs_oracle(solver, torch, blocks, which):
+def test_block_counts_vs_oracle(solver, torch, blocks, which, path):
     """Multi-block grids (grid barrier, cross-block queues) on small inputs."""
     if which == "square":
         inst = gen.square64(2)
@@ -122,18 +132,19 @@ def test_block_counts_vs_oracle(solver, torch, blocks, which):
         inst.name = "cube24"
     else:
         inst = _corner(3, 12, 3, 6, 150)
-    _say("case", inst.name, "blocks", blocks)
+    _say("case", inst.name, "blocks", blocks, "path", path)
     ref = _oracle(inst)
-    res, cnt, lab = gpu_solve(solver, torch, inst, blocks=blocks)
+    res, cnt, lab = gpu_solve(solver, torch, inst, blocks=blocks, path=path)
     _compare(inst, res, cnt, lab, ref)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("seed", [1, 2, 3])
-def test_square64_vs_oracle(solver, torch, seed):
+def test_square64_vs_oracle(solver, torch, seed, path):
     inst = gen.square64(seed)
-    _say("case", inst.name)
+    _say("case", inst.name, "path", path)
     ref = _oracle(inst)
-    res, cnt, lab = gpu_solve(solver, torch, inst)
+    res, cnt, lab = gpu_solve(solver, torch, inst, path=path)
     _compare(inst, res, cnt, lab, ref)
 
 
@@ -175,24 +186,26 @@ def _build(rec):
     raise KeyError(nm)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("name", _golden_cases())
-def test_full_size_vs_stored_oracle(solver, torch, name):
+def test_full_size_vs_stored_oracle(solver, torch, name, path):
     with open(os.path.join(GOLDEN, name + ".json")) as fh:
         rec = json.load(fh)
     inst = _build(rec)
-    _say("case", name)
-    res, cnt, lab = gpu_solve(solver, torch, inst)
+    _say("case", name, "path", path)
+    res, cnt, lab = gpu_solve(solver, torch, inst, path=path)
     assert res.tuple() == (rec["T"], rec["X"], rec["x"], rec["Y"], rec["F2"])
     assert cnt.asdict() == rec["counters"]
     assert hashlib.sha256(lab.astype("<u4").tobytes()).hexdigest() == rec["labels_sha256"]
 
 
-def test_stress_closed_form(solver, torch):
+@pytest.mark.parametrize("path", PATHS)
+def test_stress_closed_form(solver, torch, path):
     """f1 == 1 on the 256^3 cube: only straight axis-0 lines arrive by 255."""
     from tests import pins
     inst = gen.cube256_stress(22)
-    _say("case", inst.name)
-    res, cnt, lab = gpu_solve(solver, torch, inst)
+    _say("case", inst.name, "path", path)
+    res, cnt, lab = gpu_solve(solver, torch, inst, path=path)
     assert res.tuple() == pins.straight_line_answer(3, 256, inst.f2)
 
 
@@ -207,13 +220,14 @@ def test_repeat_runs_identical(solver, torch):
     assert r1.tuple() == r2.tuple() and c1.asdict() == c2.asdict() and np.array_equal(l1, l2)
 
 
-def test_pool_overflow_retry_gives_same_result(solver, torch):
+@pytest.mark.parametrize("path", PATHS)
+def test_pool_overflow_retry_gives_same_result(solver, torch, path):
     from paper_1511_06441_amd import csp
     inst = gen.square64(3)
     ref = _oracle(inst)
     csp.csp_set_pool_hint(solver.ctx, 1)
     try:
-        res, cnt, lab = gpu_solve(solver, torch, inst, blocks=4)
+        res, cnt, lab = gpu_solve(solver, torch, inst, blocks=4, path=path)
     finally:
         csp.csp_set_pool_hint(solver.ctx, 0)
     _compare(inst, res, cnt, lab, ref)
