@@ -88,6 +88,9 @@ struct Ctl {
     unsigned ror[32];
     unsigned long long rsum[16];
     unsigned flag[GMAX][32];       // per-workgroup release flags
+    unsigned long long cslot[GMAX][16];   // combining barrier: member slots
+    unsigned long long gslot[NGRP][16];   // combining barrier: group slots
+    unsigned long long cflag[GMAX][16];   // combining barrier: epoch and result per workgroup
     unsigned qslot[GMAX];          // arrival: frontier size | flags
     unsigned nslot[GMAX];          // departure: next delta (0 = none) | flags
     unsigned tslot[GMAX];          // departure: flows in transit
@@ -637,7 +640,9 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
                 }
             }
             if (!grid_sync(ctl, epoch, p.wait_limit)) { status = ST_BROKEN; break; }
-            if (lead && tid == 0) {
+            if (lead && tid == 0 && ld_rlx(&ctl->ydir) >= 2u * D) {
+                __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (lead && tid == 0) {
                 const unsigned yd = ld_rlx(&ctl->ydir);
                 const long long Y = (long long)X + p.off[yd];
                 const bool lower = (int)yd < D;
@@ -692,106 +697,163 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
 }
 
 // ===========================================================================
-// Range-owned cycle kernel (labels in LDS)
+// Range-owned cycle kernel
 //
-// Workgroup r owns the contiguous vertex range [r*c, r*c + c).  It keeps the
-// range's labels, a frontier bitmap and a B bitmap in LDS and is the only
-// writer of those labels, so deliveries are LDS atomics.  A global mirror of
-// every label (written by the owner after each arrival phase) serves
-// neighbour tests across ranges.  Flows go to the outbox of the sending range
-// for (bucket, destination offset); the receiving range reads the outboxes of
-// the ranges within K of it, using fills the senders publish after each
-// departure phase.  Nothing on the wheel is a device atomic.  The grid
-// barrier also reduces the next event time, the flows in transit and flags.
+// Workgroup r owns the contiguous vertex range [r*c, r*c + c) (ranges are
+// laid out so each XCD holds a contiguous run of them).  It keeps the
+// range's labels, a frontier bitmap and a B bitmap in LDS, and it alone
+// delivers water to the range, so deliveries are LDS atomics and every label
+// it reads for a neighbour test inside the range is already final.
+//
+// A neighbour test across ranges is shipped instead: the sender writes a
+// candidate (vertex, quality, f1, direction) to the neighbouring range, and
+// that range's owner runs the test against its own labels at the start of
+// the next cycle, before any later delivery can change them, filing the flow
+// itself if it passes.  All flows into a range therefore sit in that range's
+// own wheel (per-bucket fills in LDS), and a cycle needs one grid barrier:
+//
+//   accept candidates sent at t_prev (Steps 4-5 across ranges)
+//   deliver bucket t, commit labels, build I_t (Steps 1-3, 8)
+//   send from I_t inside the range, ship candidates out (Steps 4-5)
+//   barrier, combining the next event time, flags, counts and the best B key
+//
+// The barrier's result decides termination (Steps 6 and 1) identically in
+// every workgroup; the departure of the terminal cycle is discarded.
 // ===========================================================================
 
-struct Red {
-    unsigned mn, orf;
-    unsigned long long sum;
+constexpr int KMAX = 4;                 // neighbours lie within KMAX ranges
+constexpr int NOMAX = 2 * KMAX + 1;
+
+struct Comb {
+    unsigned mn;                        // minimum (0xFFFFFFFF = none)
+    unsigned orf;                       // bitwise or
+    unsigned long long s0, s1, s2;      // sums
+    unsigned long long mx;              // maximum
 };
 
-// Counter-tree barrier (as grid_sync) that also combines one minimum, one
-// bitwise or and one sum over all workgroups.  The releaser writes the totals
-// into every workgroup's flag line before the new epoch, so each waiter reads
-// them from its own line.  track >= 0 folds the sum into ctl->ctr[track] by
-// maximum.  Arguments must be uniform across the calling workgroup.
-__device__ bool grid_reduce(Ctl *ctl, unsigned &epoch, unsigned long long limit, unsigned mn, unsigned orf,
-                            unsigned long long sum, int track, Red &out)
+// Tree barrier over a cooperative grid that combines one Comb per
+// workgroup.  Members write their Comb to a private slot line, publish with
+// an agent-scope release fence and count themselves in their XCD group; the
+// group's last arriver combines the members' slots with one wavefront, writes
+// the group slot and counts the group at the root; the last group combines
+// the group slots and writes the result and the new epoch into every
+// workgroup's flag line.  Waits are bounded as in grid_sync.
+__device__ bool grid_combine(Ctl *ctl, unsigned &epoch, unsigned long long limit, const Comb &mine, Comb &out)
 {
     __shared__ int s_ok;
-    __shared__ unsigned s_o[4];
+    __shared__ unsigned long long s_o[6];
     __syncthreads();
     ++epoch;
     const unsigned G = gridDim.x;
     if (G == 1) {
-        out.mn = mn;
-        out.orf = orf;
-        out.sum = sum;
-        if (track >= 0 && threadIdx.x == 0 && sum > ctl->ctr[track]) ctl->ctr[track] = sum;
+        out = mine;
         return true;
     }
     if (threadIdx.x < 64) {
-        int releaser = 0;
-        unsigned rm = 0, ro = 0;
-        unsigned long long rs = 0;
-        if (threadIdx.x == 0) {
-            const unsigned grp = blockIdx.x % NGRP;
-            const unsigned ngrp = G < NGRP ? G : NGRP;
-            const unsigned members = (G - grp + NGRP - 1) / NGRP;
-            if (mn != 0xFFFFFFFFu) atomicMin(&ctl->gmin[grp][0], mn);
-            if (orf) atomicOr(&ctl->gor[grp][0], orf);
-            if (sum) atomicAdd(&ctl->gsum[grp][0], sum);
+        const unsigned lane = threadIdx.x;
+        const unsigned grp = blockIdx.x % NGRP;
+        const unsigned ngrp = G < NGRP ? G : NGRP;
+        const unsigned members = (G - grp + NGRP - 1) / NGRP;
+        int leader = 0;
+        if (lane == 0) {
+            unsigned long long *sl = ctl->cslot[blockIdx.x];
+            __hip_atomic_store(&sl[0], (unsigned long long)mine.mn | ((unsigned long long)mine.orf << 32),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sl[1], mine.s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sl[2], mine.s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sl[3], mine.s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sl[4], mine.mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned a = __hip_atomic_fetch_add(&ctl->grp[grp][0], 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (a == members - 1) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                const unsigned gm = ld_rlx(&ctl->gmin[grp][0]);
-                const unsigned go = ld_rlx(&ctl->gor[grp][0]);
-                const unsigned long long gs =
-                    __hip_atomic_load(&ctl->gsum[grp][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st_rlx(&ctl->gmin[grp][0], 0xFFFFFFFFu);
-                st_rlx(&ctl->gor[grp][0], 0u);
-                __hip_atomic_store(&ctl->gsum[grp][0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st_rlx(&ctl->grp[grp][0], 0u);
-                if (gm != 0xFFFFFFFFu) atomicMin(&ctl->rmin[0], gm);
-                if (go) atomicOr(&ctl->ror[0], go);
-                if (gs) atomicAdd(&ctl->rsum[0], gs);
+            leader = a == members - 1;
+            if (leader) st_rlx(&ctl->grp[grp][0], 0u);
+        }
+        leader = __shfl(leader, 0);
+        if (leader) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            unsigned mn = 0xFFFFFFFFu, orf = 0;
+            unsigned long long s0 = 0, s1 = 0, s2 = 0, mx = 0;
+            if (lane < members) {
+                const unsigned long long *sl = ctl->cslot[grp + NGRP * lane];
+                const unsigned long long w0 = __hip_atomic_load(&sl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                mn = (unsigned)w0;
+                orf = (unsigned)(w0 >> 32);
+                s0 = __hip_atomic_load(&sl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s1 = __hip_atomic_load(&sl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s2 = __hip_atomic_load(&sl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                mx = __hip_atomic_load(&sl[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                mn = min(mn, (unsigned)__shfl_xor(mn, o));
+                orf |= __shfl_xor(orf, o);
+                s0 += __shfl_xor(s0, o);
+                s1 += __shfl_xor(s1, o);
+                s2 += __shfl_xor(s2, o);
+                const unsigned long long om = __shfl_xor(mx, o);
+                mx = om > mx ? om : mx;
+            }
+            int releaser = 0;
+            if (lane == 0) {
+                unsigned long long *gs = ctl->gslot[grp];
+                __hip_atomic_store(&gs[0], (unsigned long long)mn | ((unsigned long long)orf << 32),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&gs[1], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&gs[2], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&gs[3], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&gs[4], mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 const unsigned rr = __hip_atomic_fetch_add(&ctl->root[0], 1u, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);
-                if (rr == ngrp - 1) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    rm = ld_rlx(&ctl->rmin[0]);
-                    ro = ld_rlx(&ctl->ror[0]);
-                    rs = __hip_atomic_load(&ctl->rsum[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    st_rlx(&ctl->rmin[0], 0xFFFFFFFFu);
-                    st_rlx(&ctl->ror[0], 0u);
-                    __hip_atomic_store(&ctl->rsum[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    st_rlx(&ctl->root[0], 0u);
-                    if (track >= 0) atomicMax(&ctl->ctr[track], rs);
-                    releaser = 1;
+                releaser = rr == ngrp - 1;
+                if (releaser) st_rlx(&ctl->root[0], 0u);
+            }
+            releaser = __shfl(releaser, 0);
+            if (releaser) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                mn = 0xFFFFFFFFu;
+                orf = 0;
+                s0 = s1 = s2 = mx = 0;
+                if (lane < ngrp) {
+                    const unsigned long long *gs = ctl->gslot[lane];
+                    const unsigned long long w0 =
+                        __hip_atomic_load(&gs[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    mn = (unsigned)w0;
+                    orf = (unsigned)(w0 >> 32);
+                    s0 = __hip_atomic_load(&gs[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s1 = __hip_atomic_load(&gs[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s2 = __hip_atomic_load(&gs[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    mx = __hip_atomic_load(&gs[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+                for (int o = 32; o > 0; o >>= 1) {
+                    mn = min(mn, (unsigned)__shfl_xor(mn, o));
+                    orf |= __shfl_xor(orf, o);
+                    s0 += __shfl_xor(s0, o);
+                    s1 += __shfl_xor(s1, o);
+                    s2 += __shfl_xor(s2, o);
+                    const unsigned long long om = __shfl_xor(mx, o);
+                    mx = om > mx ? om : mx;
+                }
+                const unsigned long long w0 = (unsigned long long)mn | ((unsigned long long)orf << 32);
+                for (unsigned i = lane; i < G; i += 64) {
+                    unsigned long long *fl = ctl->cflag[i];
+                    __hip_atomic_store(&fl[1], w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&fl[2], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&fl[3], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&fl[4], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&fl[5], mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                for (unsigned i = lane; i < G; i += 64)
+                    __hip_atomic_store(&ctl->cflag[i][0], (unsigned long long)epoch, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        releaser = __shfl(releaser, 0);
-        if (releaser) {
-            rm = __shfl(rm, 0);
-            ro = __shfl(ro, 0);
-            const unsigned slo = __shfl((unsigned)rs, 0), shi = __shfl((unsigned)(rs >> 32), 0);
-            for (unsigned i = threadIdx.x; i < G; i += 64) {
-                st_rlx(&ctl->flag[i][1], rm);
-                st_rlx(&ctl->flag[i][2], ro);
-                st_rlx(&ctl->flag[i][3], slo);
-                st_rlx(&ctl->flag[i][4], shi);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            for (unsigned i = threadIdx.x; i < G; i += 64) st_rlx(&ctl->flag[i][0], epoch);
-        }
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             int ok = 1;
+            unsigned long long *fl = ctl->cflag[blockIdx.x];
             const unsigned long long t0 = wall_clock64();
-            while (ld_rlx(&ctl->flag[blockIdx.x][0]) < epoch) {
+            while (__hip_atomic_load(&fl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned long long)epoch) {
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > limit) {
                     __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -801,26 +863,24 @@ __device__ bool grid_reduce(Ctl *ctl, unsigned &epoch, unsigned long long limit,
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (__hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-            s_o[0] = ld_rlx(&ctl->flag[blockIdx.x][1]);
-            s_o[1] = ld_rlx(&ctl->flag[blockIdx.x][2]);
-            s_o[2] = ld_rlx(&ctl->flag[blockIdx.x][3]);
-            s_o[3] = ld_rlx(&ctl->flag[blockIdx.x][4]);
+            for (int k = 0; k < 5; ++k)
+                s_o[k] = __hip_atomic_load(&fl[1 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_ok = ok;
         }
     }
     __syncthreads();
-    out.mn = s_o[0];
-    out.orf = s_o[1];
-    out.sum = (unsigned long long)s_o[2] | ((unsigned long long)s_o[3] << 32);
+    out.mn = (unsigned)s_o[0];
+    out.orf = (unsigned)(s_o[0] >> 32);
+    out.s0 = s_o[1];
+    out.s1 = s_o[2];
+    out.s2 = s_o[3];
+    out.mx = s_o[4];
     const bool ok = s_ok != 0;
     __syncthreads();
     return ok;
 }
 
-constexpr int KMAX = 4;                 // largest range offset of a neighbour
-constexpr int NOMAX = 2 * KMAX + 1;
-
-struct P3 {
+struct PR {
     long long N;
     long long off[8];              // neighbour offset per direction
     long long offq[8];             // floor(off / c)
@@ -831,11 +891,12 @@ struct P3 {
     const void *rec;
     const uint8_t *A, *B;
     unsigned M;
-    unsigned *mirror;              // every label, written by its owner only
     unsigned *lists;               // [G][c] frontier list per range
-    uint2 *pool;                   // [G][W][NO][S] outboxes
+    uint2 *pool;                   // [G][W][S] wheel of each range
     unsigned long long pool_flows;
-    unsigned *pub;                 // [G][MAXW][NO] published outbox fills
+    uint2 *cand;                   // [2][G][NO][cand_cap] candidates by sender and offset
+    unsigned cand_cap;
+    unsigned *pubc;                // [2][G][NOMAX] candidate fills
     Ctl *ctl;
     unsigned *labels_out;
     long long max_cycles;
@@ -867,19 +928,22 @@ __device__ __forceinline__ bool lab_raise(uint16_t *lab, unsigned i, unsigned q)
     }
 }
 
+constexpr unsigned CAND_LI = 0x1FFFFu;     // candidate word 0: local index | f1 << 17 | dir << 25
+
 template <int D, typename LT>
-__global__ void __launch_bounds__(BLOCK) k_solve_lds(P3 p)
+__global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
 {
     using RT = typename Rec<D>::T;
     extern __shared__ unsigned smem[];
     __shared__ unsigned s_wave[NWAVES];
     __shared__ unsigned s_flags;
     __shared__ unsigned s_min;
-    __shared__ unsigned long long s_sum;
+    __shared__ unsigned s_ydir;
     __shared__ unsigned long long s_xkey;
+    __shared__ unsigned long long s_sum;
     __shared__ unsigned long long s_red[4];
-    __shared__ unsigned s_src[NOMAX];
-    __shared__ unsigned s_pre[NOMAX + 1];
+    __shared__ unsigned s_ccnt[NOMAX];        // candidates shipped this cycle, by offset
+    __shared__ unsigned s_cpre[NOMAX + 1];    // incoming candidates, prefix by sender
 
     Ctl *ctl = p.ctl;
     const unsigned tid = threadIdx.x, lane = lane_id();
@@ -897,34 +961,44 @@ __global__ void __launch_bounds__(BLOCK) k_solve_lds(P3 p)
     unsigned W = 2;
     while (W <= ctl->maxf1) W <<= 1;
     const unsigned Wm = W - 1;
-    const unsigned long long S = p.pool_flows / ((unsigned long long)G * W * NO);
+    const unsigned long long S = p.pool_flows / ((unsigned long long)G * W);
+    const unsigned CS = p.cand_cap;
 
-    // LDS: labels | frontier bitmap | B bitmap | outbox fills [MAXW][NO] | dirty bits
+    // LDS: labels | frontier bitmap | B bitmap | wheel fills [MAXW]
     const unsigned cw = (unsigned)((c + 31) / 32);
     const unsigned lab_words = (unsigned)((c * (long long)sizeof(LT) + 3) / 4);
     LT *lab = reinterpret_cast<LT *>(smem);
     unsigned *fb = smem + lab_words;
     unsigned *bb = fb + cw;
     unsigned *cnt = bb + cw;
-    unsigned *dirty = cnt + MAXW * NO;
-    const unsigned ndirty = (MAXW * NO + 31) / 32;
     unsigned *mylist = p.lists + (unsigned long long)r * c;
-    unsigned *mypub = p.pub + (unsigned long long)r * MAXW * NO;
-    auto outbox = [&](unsigned long long src, unsigned bk, unsigned oi) {
-        return p.pool + ((src * W + bk) * (unsigned long long)NO + oi) * S;
+    uint2 *wheel = p.pool + (unsigned long long)r * W * S;
+    auto candbuf = [&](unsigned par, unsigned long long src, unsigned oi) {
+        return p.cand + (((unsigned long long)par * G + src) * NO + oi) * CS;
+    };
+    auto pubc = [&](unsigned par, unsigned long long src, unsigned oi) {
+        return p.pubc + ((unsigned long long)par * G + src) * NOMAX + oi;
     };
 
-    unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread
-    unsigned long long cC = 0;                              // lead workgroup, thread 0
+    unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread, committed
+    unsigned long long cC = 0, cP = 0, cI = 0;              // every workgroup, from the barrier
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
     const bool timing = p.prof && lead && tid == 0;
+#define PHASE4(k)                                            \
+    do {                                                     \
+        if (timing) {                                        \
+            const unsigned long long now_ = wall_clock64();  \
+            ph[k] += now_ - ph_t;                            \
+            ph_t = now_;                                     \
+        }                                                    \
+    } while (0)
 
-    for (unsigned i = tid; i < lab_words + 2 * cw + MAXW * NO + ndirty; i += BLOCK) smem[i] = 0;
-    for (unsigned i = tid; i < MAXW * NO; i += BLOCK) mypub[i] = 0;
+    for (unsigned i = tid; i < lab_words + 2 * cw + MAXW; i += BLOCK) smem[i] = 0;
+    if (tid < 2 * NOMAX) p.pubc[((unsigned long long)(tid / NOMAX) * G + r) * NOMAX + tid % NOMAX] = 0;
     if (tid == 0) {
         s_flags = 0;
         s_xkey = 0;
-        for (int i = 0; i < 4; ++i) s_red[i] = 0;
+        s_ydir = 0xFFFFFFFFu;
     }
     __syncthreads();
 
@@ -941,13 +1015,12 @@ __global__ void __launch_bounds__(BLOCK) k_solve_lds(P3 p)
                 atomicOr(&fb[i >> 5], 1u << (i & 31));
             }
             if (b) atomicOr(&bb[i >> 5], 1u << (i & 31));
-            p.mirror[v] = a ? p.M : 0u;
         }
     }
     __syncthreads();
 
-    // Frontier bitmap -> sorted list of local indices; publish improved labels
-    // to the mirror; clear the bitmap; best (label, -index) among B members.
+    // Frontier bitmap -> sorted list of local indices; clear the bitmap;
+    // best (label, -index) over the B members in it.
     auto compact = [&]() -> unsigned {
         unsigned total = 0;
         unsigned long long bestB = 0;
@@ -967,11 +1040,9 @@ __global__ void __launch_bounds__(BLOCK) k_solve_lds(P3 p)
                 bits &= bits - 1u;
                 const unsigned i = wi * 32u + bt;
                 mylist[k++] = i;
-                const unsigned L = lab_get(lab, i);
-                p.mirror[base + i] = L;
                 if ((bm >> bt) & 1u) {
-                    const unsigned long long key =
-                        ((unsigned long long)L << 32) | (0xFFFFFFFFull - (unsigned long long)(base + i));
+                    const unsigned long long key = ((unsigned long long)lab_get(lab, i) << 32) |
+                                                   (0xFFFFFFFFull - (unsigned long long)(base + i));
                     bestB = key > bestB ? key : bestB;
                 }
             }
@@ -990,221 +1061,222 @@ __global__ void __launch_bounds__(BLOCK) k_solve_lds(P3 p)
     };
 
     unsigned nlist = 0;
-    Red red;
     if (status == ST_RUNNING) {
         nlist = compact();
         if (tid == 0) cU += nlist;
-        const unsigned fl = s_flags;
-        if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, fl & SF_INVAL, 0, -1, red)) status = ST_BROKEN;
-        else if (red.orf & SF_INVAL) status = ST_INVAL;
     }
 
-    long long t = 0;
-    unsigned cyc = 0;
-    unsigned b_cur = 0;
+    long long t = 0, t_prev = 0;
+    unsigned cyc = 0, par = 0;
+    unsigned F = 0;                     // flows delivered this cycle
+    unsigned long long transit = 0;     // flows in transit after the previous sending round
+    bool found = false;
     if (timing) ph_t = wall_clock64();
-#define PHASE3(k)                                            \
-    do {                                                     \
-        if (timing) {                                        \
-            const unsigned long long now_ = wall_clock64();  \
-            ph[k] += now_ - ph_t;                            \
-            ph_t = now_;                                     \
-        }                                                    \
-    } while (0)
 
     while (status == ST_RUNNING) {
-        // ---- Departure (Steps 4-5, Algorithms 7-8) from I_t within this range.
-        {
-            // the bucket delivered at t is free again
-            const unsigned bt = (unsigned)(t & Wm);
-            if (tid < (unsigned)NO) {
-                const unsigned k = bt * NO + tid;
-                if (cnt[k]) {
-                    cnt[k] = 0;
-                    if ((int)tid != K) atomicOr(&dirty[k >> 5], 1u << (k & 31));
-                }
-            }
-            __syncthreads();
-            for (unsigned j = tid; j < nlist; j += BLOCK) {
-                const unsigned i = mylist[j];
-                const long long Q = base + i;
-                const unsigned L = lab_get(lab, i);
-                const RT rv = rec[Q];
-                unsigned lp[2 * D];
-                int oo[2 * D];
+        // ---- Departure (Steps 4-5, Algorithms 7-8) from I_t in this range.
+        unsigned long long dD = 0, dE = 0;
+        if (tid < NOMAX) s_ccnt[tid] = 0;
+        if (tid == 0) s_min = 0xFFFFFFFFu;
+        __syncthreads();
+        for (unsigned j = tid; j < nlist; j += BLOCK) {
+            const unsigned i = mylist[j];
+            const long long Q = base + i;
+            const unsigned L = lab_get(lab, i);
+            const RT rv = rec[Q];
 #pragma unroll
-                for (int dir = 0; dir < 2 * D; ++dir) {
-                    unsigned a1, a2;
-                    rec_get<D>(rv, dir, a1, a2);
-                    oo[dir] = 0;
-                    lp[dir] = 0xFFFFFFFFu;
-                    if (a1) {
-                        const long long lo = (long long)i + p.offr[dir];
-                        const int o = (int)p.offq[dir] + (lo >= c ? 1 : 0);
-                        oo[dir] = o;
-                        lp[dir] = o == 0 ? lab_get(lab, (unsigned)(lo >= c ? lo - c : lo))
-                                         : p.mirror[Q + p.off[dir]];
+            for (int dir = 0; dir < 2 * D; ++dir) {
+                unsigned a1, a2;
+                rec_get<D>(rv, dir, a1, a2);
+                if (!a1) continue;
+                ++dD;
+                const int q = (int)L - (int)a2;
+                if (q <= 0) continue;
+                const long long lo = (long long)i + p.offr[dir];
+                const int o = (int)p.offq[dir] + (lo >= c ? 1 : 0);
+                const unsigned li = (unsigned)(lo >= c ? lo - c : lo);   // index in the owner's range
+                const unsigned rdir = (unsigned)(2 * D - 1 - dir);      // sender seen from the receiver
+                if (o == 0) {
+                    if ((unsigned)q > lab_get(lab, li)) {
+                        const unsigned bk = (unsigned)((t + a1) & Wm);
+                        const unsigned pos = atomicAdd(&cnt[bk], 1u);
+                        if (pos < S)
+                            wheel[(unsigned long long)bk * S + pos] =
+                                make_uint2((unsigned)(base + li), ((unsigned)q << 3) | rdir);
+                        else
+                            atomicOr(&s_flags, SF_OVER);
+                        ++dE;
                     }
-                }
-#pragma unroll
-                for (int dir = 0; dir < 2 * D; ++dir) {
-                    unsigned a1, a2;
-                    rec_get<D>(rv, dir, a1, a2);
-                    if (a1) {
-                        ++cD;
-                        const int q = (int)L - (int)a2;
-                        if (q > (int)lp[dir]) {
-                            const unsigned bk = (unsigned)((t + a1) & Wm);
-                            const unsigned oi = (unsigned)(oo[dir] + K);
-                            const unsigned k = bk * NO + oi;
-                            const unsigned pos = atomicAdd(&cnt[k], 1u);
-                            if (pos < S) {
-                                // the receiver sees the sender in the opposite direction
-                                outbox(r, bk, oi)[pos] =
-                                    make_uint2((unsigned)(Q + p.off[dir]),
-                                               ((unsigned)q << 3) | (unsigned)(2 * D - 1 - dir));
-                            } else {
-                                atomicOr(&s_flags, SF_OVER);
-                            }
-                            if (oi != (unsigned)K) atomicOr(&dirty[k >> 5], 1u << (k & 31));
-                            ++cE;
-                        }
-                    }
+                } else {
+                    const unsigned oi = (unsigned)(o + K);
+                    const unsigned pos = atomicAdd(&s_ccnt[oi], 1u);
+                    if (pos < CS)
+                        candbuf(par, r, oi)[pos] = make_uint2(li | (a1 << 17) | (rdir << 25), (unsigned)q);
+                    else
+                        atomicOr(&s_flags, SF_OVER);
+                    atomicMin(&s_min, a1);
                 }
             }
         }
         __syncthreads();
-        // publish changed remote fills; next delivery time; flows in transit
+        // publish candidate fills; next delivery time seen from this range
+        if (tid < (unsigned)NO && (int)tid != K) {
+            const unsigned v = s_ccnt[tid];
+            if (v > CS) atomicOr(&s_flags, SF_OVER);
+            __hip_atomic_store(pubc(par, r, tid), min(v, CS), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         {
-            for (unsigned wd = tid; wd < ndirty; wd += BLOCK) {
-                unsigned bits = dirty[wd];
-                if (bits) {
-                    dirty[wd] = 0;
-                    while (bits) {
-                        const unsigned bt = (unsigned)(__ffs(bits) - 1);
-                        bits &= bits - 1u;
-                        const unsigned k = wd * 32u + bt;
-                        st_rlx(&mypub[k], cnt[k]);
-                    }
-                }
-            }
-            if (tid == 0) {
-                s_min = 0xFFFFFFFFu;
-                s_sum = 0;
-            }
-            __syncthreads();
             unsigned best = 0xFFFFFFFFu, over = 0;
-            unsigned long long tr = 0;
-            for (unsigned k = tid; k < W * (unsigned)NO; k += BLOCK) {
-                const unsigned v = cnt[k];
+            for (unsigned bk = tid; bk < W; bk += BLOCK) {
+                const unsigned v = cnt[bk];
                 if (v) {
-                    const unsigned bk = k / (unsigned)NO;
                     const unsigned delta = (unsigned)((bk - (unsigned)t) & Wm);
-                    best = delta < best ? delta : best;
-                    tr += v;
+                    best = min(best, delta);
                     if (v > S) over = 1;
                 }
             }
             for (int o = 32; o > 0; o >>= 1) {
                 best = min(best, (unsigned)__shfl_xor(best, o));
-                tr += __shfl_xor(tr, o);
                 over |= __shfl_xor(over, o);
             }
             if (lane == 0) {
                 if (best != 0xFFFFFFFFu) atomicMin(&s_min, best);
-                if (tr) atomicAdd(&s_sum, tr);
                 if (over) atomicOr(&s_flags, SF_OVER);
             }
-            __syncthreads();
-        }
-        PHASE3(0);
-        const unsigned my_min = s_min;
-        const unsigned my_fl = s_flags & SF_OVER;
-        const unsigned long long my_tr = s_sum;
-        if (!grid_reduce(ctl, epoch, p.wait_limit, my_min, my_fl, my_tr, 5, red)) { status = ST_BROKEN; break; }
-        PHASE3(1);
-
-        // ---- Step 1 (Algorithm 4): the earliest bucket anywhere.
-        if (red.orf & SF_OVER) { status = ST_OVERFLOW; break; }
-        if (red.mn == 0xFFFFFFFFu) { status = ST_DONE; break; }            // condition 2
-        if (p.max_cycles > 0 && (long long)cyc >= p.max_cycles) { status = ST_CANCELED; break; }
-        t += red.mn;
-        ++cyc;
-        if (lead && tid == 0) ++cC;
-        b_cur = (unsigned)(t & Wm);
-        if (tid == 0) s_flags = 0;
-        PHASE3(2);
-
-        // ---- Arrival (Steps 1-3 and 8, Algorithms 4-6, 10): flows for this range.
-        if (tid < (unsigned)NO) {
-            const int o = (int)tid - K;                   // sender range r + o
-            const long long src = (long long)r + o;
-            unsigned v = 0;
-            if (o == 0) v = cnt[b_cur * NO + K];
-            else if (src >= 0 && src < (long long)G)
-                v = ld_rlx(&p.pub[((unsigned long long)src * MAXW + b_cur) * NO + (unsigned)(K - o)]);
-            s_src[tid] = v;
         }
         __syncthreads();
-        if (tid == 0) {
-            s_pre[0] = 0;
-            for (int oi = 0; oi < NO; ++oi) s_pre[oi + 1] = s_pre[oi] + s_src[oi];
-        }
-        __syncthreads();
-        const unsigned *pre = s_pre;
-        const unsigned F = pre[NO];
-        for (unsigned j = tid; j < F; j += BLOCK) {
-            int oi = 0;
-            while (j >= pre[oi + 1]) ++oi;
-            const long long src = (long long)r + (oi - K);
-            const uint2 f = outbox((unsigned long long)src, b_cur, (unsigned)(2 * K - oi))[j - pre[oi]];
-            const unsigned i = (unsigned)((long long)f.x - base);
-            if (lab_raise(lab, i, f.y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
-        }
-        if (tid == 0) cR += F;
-        __syncthreads();
-        nlist = compact();
-        if (tid == 0) cU += nlist;
-        PHASE3(3);
-        const unsigned fl = s_flags & SF_BHIT;
-        if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, fl, nlist, 6, red)) { status = ST_BROKEN; break; }
-        PHASE3(4);
+        PHASE4(0);
+        Comb mine, all;
+        mine.mn = s_min;
+        mine.orf = s_flags & (SF_OVER | SF_BHIT | SF_INVAL);
+        mine.s0 = F;
+        mine.s1 = nlist;
+        mine.s2 = transit;
+        mine.mx = s_xkey;
+        if (!grid_combine(ctl, epoch, p.wait_limit, mine, all)) { status = ST_BROKEN; break; }
+        PHASE4(1);
 
-        // ---- Step 6 (Algorithm 2): a vertex of B improved -> T = t.
-        if (red.orf & SF_BHIT) {
-            if (tid == 0 && s_xkey) atomicMax(&ctl->xkey, s_xkey);
-            if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, 0, 0, -1, red)) { status = ST_BROKEN; break; }
-            const unsigned long long xk =
-                __hip_atomic_load(&ctl->xkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned X = (unsigned)(0xFFFFFFFFull - (xk & 0xFFFFFFFFull));
-            const unsigned LX = (unsigned)(xk >> 32);
+        if (all.orf & SF_INVAL) { status = ST_INVAL; break; }          // A and B overlap
+        if (all.orf & SF_OVER) { status = ST_OVERFLOW; break; }
+        if (cyc > 0) {
+            cC += all.s0 > 0 ? 1 : 0;
+            cI = all.s1 > cI ? all.s1 : cI;
+            cP = all.s2 > cP ? all.s2 : cP;
+        }
+        if (all.orf & SF_BHIT) {
+            // ---- Step 6 (Algorithm 2): T = t.  The departure just made is
+            // not part of the run; x is the delivery to X carrying its label
+            // from the smallest sender, found by X's owner.
+            found = true;
+            const unsigned X = (unsigned)(0xFFFFFFFFull - (all.mx & 0xFFFFFFFFull));
+            const unsigned LX = (unsigned)(all.mx >> 32);
             if ((long long)X >= base && (long long)X < base + (long long)cr) {
+                const uint2 *bkt = wheel + (unsigned long long)(t & Wm) * S;
                 for (unsigned j = tid; j < F; j += BLOCK) {
-                    int oi = 0;
-                    while (j >= pre[oi + 1]) ++oi;
-                    const long long src = (long long)r + (oi - K);
-                    const uint2 f = outbox((unsigned long long)src, b_cur, (unsigned)(2 * K - oi))[j - pre[oi]];
-                    if (f.x == X && (f.y >> 3) == LX) atomicMin(&ctl->ydir, f.y & 7u);
+                    const uint2 f = bkt[j];
+                    if (f.x == X && (f.y >> 3) == LX) atomicMin(&s_ydir, f.y & 7u);
                 }
-            }
-            if (!grid_reduce(ctl, epoch, p.wait_limit, 0xFFFFFFFFu, 0, 0, -1, red)) { status = ST_BROKEN; break; }
-            if (lead && tid == 0) {
-                const unsigned yd = ld_rlx(&ctl->ydir);
-                const long long Y = (long long)X + p.off[yd];
-                const bool lower = (int)yd < D;
-                const int k = lower ? D - 1 - (int)yd : (int)yd - D;
-                ctl->res[0] = t;
-                ctl->res[1] = X;
-                ctl->res[2] = (long long)k * N + (lower ? Y : (long long)X);
-                ctl->res[3] = Y;
-                ctl->res[4] = (long long)p.M - (long long)LX;
+                __syncthreads();
+                if (tid == 0 && s_ydir >= 2u * D) {
+                    __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else if (tid == 0) {
+                    const unsigned yd = s_ydir;
+                    const long long Y = (long long)X + p.off[yd];
+                    const bool lower = (int)yd < D;
+                    const int k = lower ? D - 1 - (int)yd : (int)yd - D;
+                    ctl->res[0] = t;
+                    ctl->res[1] = X;
+                    ctl->res[2] = (long long)k * N + (lower ? Y : (long long)X);
+                    ctl->res[3] = Y;
+                    ctl->res[4] = (long long)p.M - (long long)LX;
+                }
             }
             status = ST_DONE;
             break;
         }
-        PHASE3(5);
+        cD += dD;
+        cE += dE;
+        if (all.mn == 0xFFFFFFFFu) { status = ST_DONE; break; }          // condition 2
+        if (p.max_cycles > 0 && (long long)cyc >= p.max_cycles) { status = ST_CANCELED; break; }
+        t_prev = t;
+        t += all.mn;
+        ++cyc;
+
+        // ---- Steps 4-5 across ranges: test candidates shipped at t_prev
+        // against this range's labels (still L_{t_prev}) and file the flows.
+        if (tid < (unsigned)NO) {
+            const int dd = (int)tid - K;                 // sender range r + dd
+            const long long src = (long long)r + dd;
+            unsigned v = 0;
+            if (dd != 0 && src >= 0 && src < (long long)G)
+                v = __hip_atomic_load(pubc(par, (unsigned long long)src, (unsigned)(K - dd)), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            s_ccnt[tid] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_cpre[0] = 0;
+            for (int oi = 0; oi < NO; ++oi) s_cpre[oi + 1] = s_cpre[oi] + s_ccnt[oi];
+        }
+        __syncthreads();
+        {
+            const unsigned FC = s_cpre[NO];
+            for (unsigned j = tid; j < FC; j += BLOCK) {
+                int oi = 0;
+                while (j >= s_cpre[oi + 1]) ++oi;
+                const long long src = (long long)r + (oi - K);
+                const uint2 cd = candbuf(par, (unsigned long long)src, (unsigned)(2 * K - oi))[j - s_cpre[oi]];
+                const unsigned li = cd.x & CAND_LI, a1 = (cd.x >> 17) & 0xFFu, rdir = cd.x >> 25;
+                if (cd.y > lab_get(lab, li)) {
+                    const unsigned bk = (unsigned)((t_prev + a1) & Wm);
+                    const unsigned pos = atomicAdd(&cnt[bk], 1u);
+                    if (pos < S)
+                        wheel[(unsigned long long)bk * S + pos] = make_uint2((unsigned)(base + li), (cd.y << 3) | rdir);
+                    else
+                        atomicOr(&s_flags, SF_OVER);
+                    ++cE;
+                }
+            }
+        }
+        par ^= 1u;
+        if (tid == 0) s_sum = 0;
+        __syncthreads();
+        PHASE4(2);
+        // flows in transit after the sending round at t_prev
+        {
+            unsigned long long tr = 0;
+            for (unsigned bk = tid; bk < W; bk += BLOCK) tr += cnt[bk];
+            for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
+            if (lane == 0 && tr) atomicAdd(&s_sum, tr);
+        }
+
+        // ---- Arrival (Steps 1-3 and 8, Algorithms 4-6, 10): deliver bucket t.
+        {
+            const unsigned bk = (unsigned)(t & Wm);
+            F = (unsigned)min((unsigned long long)cnt[bk], S);
+            const uint2 *bkt = wheel + (unsigned long long)bk * S;
+            for (unsigned j = tid; j < F; j += BLOCK) {
+                const uint2 f = bkt[j];
+                const unsigned i = (unsigned)((long long)f.x - base);
+                if (lab_raise(lab, i, f.y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
+            }
+            if (tid == 0) cR += F;
+            __syncthreads();
+            if (tid == 0) {
+                cnt[bk] = 0;
+                transit = s_sum;
+                s_flags &= SF_OVER;
+                s_xkey = 0;
+            }
+            __syncthreads();
+            transit = s_sum;
+        }
+        PHASE4(3);
+        nlist = compact();
+        if (tid == 0) cU += nlist;
+        PHASE4(4);
     }
-#undef PHASE3
+#undef PHASE4
 
     // ---- outputs
     if (status == ST_DONE && p.labels_out) {
@@ -1228,9 +1300,11 @@ __global__ void __launch_bounds__(BLOCK) k_solve_lds(P3 p)
         if (lead) {
             for (int i = 0; i < 6; ++i) ctl->prof[i] = ph[i];
             ctl->ctr[0] = cC;
+            ctl->ctr[5] = cP;
+            ctl->ctr[6] = cI;
             const int br = __hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ctl->status = br ? ST_BROKEN : status;
-            if (status == ST_DONE && ctl->xkey == 0) {
+            if (status == ST_DONE && !found) {
                 for (int i = 0; i < 5; ++i) ctl->res[i] = -1;
             }
         }
@@ -1274,8 +1348,11 @@ struct csp_ctx {
     int path_override = 0;          // 0 auto, 1 LDS ranges, 2 global labels
     int last_path = 0;
     size_t lds_limit = 65536;
-    unsigned *pub = nullptr;
+    unsigned *pub = nullptr;        // candidate fills [2][G][NOMAX]
     size_t pub_cap = 0;
+    uint2 *cand = nullptr;          // candidates [2][G][NO][cap]
+    size_t cand_cap = 0;
+    unsigned long long cand_seen = 0;
     unsigned long long pool_flows_seen = 0;   // largest pool a solve needed so far
     char err[256] = {0};
 };
@@ -1316,17 +1393,17 @@ const void *lds_kernel(int d, int lt)
 {
     if (lt == 2) {
         switch (d) {
-        case 1: return (const void *)k_solve_lds<1, uint16_t>;
-        case 2: return (const void *)k_solve_lds<2, uint16_t>;
-        case 3: return (const void *)k_solve_lds<3, uint16_t>;
-        default: return (const void *)k_solve_lds<4, uint16_t>;
+        case 1: return (const void *)k_ranges<1, uint16_t>;
+        case 2: return (const void *)k_ranges<2, uint16_t>;
+        case 3: return (const void *)k_ranges<3, uint16_t>;
+        default: return (const void *)k_ranges<4, uint16_t>;
         }
     }
     switch (d) {
-    case 1: return (const void *)k_solve_lds<1, unsigned>;
-    case 2: return (const void *)k_solve_lds<2, unsigned>;
-    case 3: return (const void *)k_solve_lds<3, unsigned>;
-    default: return (const void *)k_solve_lds<4, unsigned>;
+    case 1: return (const void *)k_ranges<1, unsigned>;
+    case 2: return (const void *)k_ranges<2, unsigned>;
+    case 3: return (const void *)k_ranges<3, unsigned>;
+    default: return (const void *)k_ranges<4, unsigned>;
     }
 }
 
@@ -1343,11 +1420,10 @@ struct LdsPlan {
 
 size_t lds_bytes_for(long long c, int K, int lt)
 {
+    (void)K;
     const long long cw = (c + 31) / 32;
     const long long lab_words = (c * lt + 3) / 4;
-    const long long NO = 2 * K + 1;
-    const long long ndirty = (MAXW * NO + 31) / 32;
-    return (size_t)(4 * (lab_words + 2 * cw + MAXW * NO + ndirty));
+    return (size_t)(4 * (lab_words + 2 * cw + MAXW));
 }
 
 LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M, int G_want);
@@ -1472,7 +1548,7 @@ void csp_destroy(csp_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     for (void *p : {(void *)ctx->lab, (void *)ctx->rec, (void *)ctx->queue, (void *)ctx->pool,
-                    (void *)ctx->ctl, (void *)ctx->in_buf, (void *)ctx->pub})
+                    (void *)ctx->ctl, (void *)ctx->in_buf, (void *)ctx->pub, (void *)ctx->cand})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)ctx->h_ctl, (void *)ctx->h_byte})
         if (p) (void)hipHostFree(p);
@@ -1535,12 +1611,19 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     // 16 flows per directed-edge endpoint; doubled on overflow up to the
     // bound at which no bucket can overflow
     const unsigned long long NO = use_lds ? (unsigned long long)(2 * plan.K + 1) : 1ull;
-    unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G * NO
+    unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G
                                              : std::max<unsigned long long>(
                                                    std::max<unsigned long long>(1ull << 20, 16ull * d * N),
                                                    ctx->pool_flows_seen);
-    const unsigned long long pool_max = 2ull * d * N * 256ull * G * NO + (1ull << 20);
+    const unsigned long long pool_max = 2ull * d * N * 256ull * G + (1ull << 20);
     unsigned long long qs = std::max<unsigned long long>((N + G - 1) / G, 4096ull);
+    // candidates per (sender, offset) and cycle: at most 2d per vertex of the range
+    const unsigned long long cand_max = use_lds ? 2ull * d * (unsigned long long)plan.c : 0ull;
+    unsigned long long ccap = use_lds ? std::min<unsigned long long>(
+                                            cand_max, std::max<unsigned long long>(
+                                                          {4096ull, (unsigned long long)plan.c / 2, ctx->cand_seen}))
+                                      : 0ull;
+    if (use_lds && ctx->pool_hint) ccap = std::min<unsigned long long>(cand_max, 64ull);
 
     for (;;) {
         rc = grow(ctx, &ctx->pool, ctx->pool_cap, (size_t)pool, "transit pool");
@@ -1551,9 +1634,11 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         if (use_lds) {
             rc = grow(ctx, &ctx->queue, ctx->queue_cap, (size_t)(plan.c * G), "frontier");
             if (rc) return rc;
-            rc = grow(ctx, &ctx->pub, ctx->pub_cap, (size_t)G * MAXW * NOMAX, "published fills");
+            rc = grow(ctx, &ctx->pub, ctx->pub_cap, (size_t)2 * G * NOMAX, "candidate fills");
             if (rc) return rc;
-            P3 p;
+            rc = grow(ctx, &ctx->cand, ctx->cand_cap, (size_t)(2ull * G * NO * ccap), "candidates");
+            if (rc) return rc;
+            PR p;
             memset(&p, 0, sizeof(p));
             p.N = N;
             p.c = plan.c;
@@ -1569,11 +1654,12 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             p.A = A;
             p.B = B;
             p.M = M;
-            p.mirror = ctx->lab;
             p.lists = ctx->queue;
             p.pool = ctx->pool;
             p.pool_flows = pool;
-            p.pub = ctx->pub;
+            p.cand = ctx->cand;
+            p.cand_cap = (unsigned)ccap;
+            p.pubc = ctx->pub;
             p.ctl = ctx->ctl;
             p.labels_out = labels;
             p.max_cycles = max_cycles;
@@ -1618,15 +1704,20 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             return fail(ctx, CSP_EINVAL, c.bad ? "an edge has f1 or f2 equal to 0" : "A and B overlap");
         }
         if (c.status == ST_OVERFLOW) {
-            if (pool >= pool_max) return fail(ctx, CSP_EOVERFLOW, "transit pool overflow at the edge bound");
+            if (pool >= pool_max && ccap >= cand_max)
+                return fail(ctx, CSP_EOVERFLOW, "transit pool overflow at the edge bound");
             pool = std::min(pool * 2, pool_max);
             qs = std::min<unsigned long long>(qs * 2, (unsigned long long)N);
+            ccap = std::min(ccap * 2, cand_max);
             continue;
         }
         if (c.status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
-        if (c.status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out");
+        if (c.status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out or inconsistent result");
         if (c.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "solve did not finish");
-        if (!ctx->pool_hint) ctx->pool_flows_seen = std::max(ctx->pool_flows_seen, pool);
+        if (!ctx->pool_hint) {
+            ctx->pool_flows_seen = std::max(ctx->pool_flows_seen, pool);
+            ctx->cand_seen = std::max(ctx->cand_seen, ccap);
+        }
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
         for (int i = 0; i < 8; ++i) ctx->last_prof[i] = c.prof[i];
         out->T = c.res[0];
