@@ -115,6 +115,27 @@ int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n,
                         int64_t *path, int64_t cap, int64_t *len,
                         csp_result *out, void *stream);
 
+/* One problem of a batch: device pointers laid out as for csp_solve_dev.
+ * labels (nullable) is a device uint32 [n^d] output. */
+typedef struct {
+    int d;
+    int64_t n;
+    const uint8_t *f1, *f2, *A, *B;
+    uint32_t M;
+    uint32_t *labels;
+} csp_problem;
+
+/* Many independent solves (sections 4-6, Algorithm 1 for each) in one
+ * persistent launch per dimension.  Workgroups take (problem, range) work
+ * items, largest problems first; a problem whose lattice does not fit one
+ * workgroup's LDS runs on a gang of workgroups that synchronise only among
+ * themselves.  Results (and counters, nullable) are written per problem in
+ * input order, identical to csp_solve_dev on each problem alone.  Returns
+ * the first error; problems whose wheel overflows are re-run with larger
+ * pools automatically.  Synchronous on `stream`. */
+int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs,
+                    csp_result *out, csp_counters *cnt, void *stream);
+
 /* Device time (ms, from HIP events on the solve stream) of the cycle kernel
  * of the last successful csp_solve_dev on ctx; excludes input checks and
  * result copies. */

@@ -26,7 +26,7 @@ EXPORTED = (
     "csp_create", "csp_destroy", "csp_last_error", "csp_solve_dev", "csp_solve",
     "csp_reconstruct_dev", "csp_last_kernel_ms", "csp_set_pool_hint",
     "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us", "csp_set_path",
-    "csp_last_path",
+    "csp_last_path", "csp_solve_batch",
 )
 
 
@@ -36,6 +36,12 @@ class csp_result(ctypes.Structure):
 
     def tuple(self):
         return (self.T, self.X, self.x, self.Y, self.F2)
+
+
+class csp_problem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int64), ("f1", ctypes.c_void_p),
+                ("f2", ctypes.c_void_p), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("M", ctypes.c_uint32), ("labels", ctypes.c_void_p)]
 
 
 class csp_counters(ctypes.Structure):
@@ -71,6 +77,8 @@ def _load():
     lib.csp_set_pool_hint.restype = i32
     lib.csp_set_blocks.argtypes = [p, i32]
     lib.csp_set_blocks.restype = i32
+    lib.csp_solve_batch.argtypes = [p, i32, p, p, p, p]
+    lib.csp_solve_batch.restype = i32
     lib.csp_set_path.argtypes = [p, i32]
     lib.csp_set_path.restype = i32
     lib.csp_last_path.argtypes = [p]
@@ -157,6 +165,22 @@ def csp_reconstruct_dev(ctx, d, n, f1, f2, A, B, M, scratch_mask, cap, stream=No
                                  ctypes.byref(ln), ctypes.byref(res), _stream(stream))
     _check(ctx, rc)
     return path[:ln.value].copy(), res
+
+
+def csp_solve_batch(ctx, instances, labels=None, counters=True, stream=None):
+    """instances: list of DeviceInstance; labels: optional list of device int32 tensors (or None)."""
+    k = len(instances)
+    probs = (csp_problem * k)()
+    for i, di in enumerate(instances):
+        probs[i] = csp_problem(di.d, di.n, di.f1.data_ptr(), di.f2.data_ptr(), di.A.data_ptr(),
+                               di.B.data_ptr(), di.M,
+                               labels[i].data_ptr() if labels is not None and labels[i] is not None else None)
+    res = (csp_result * k)()
+    cnt = (csp_counters * k)() if counters else None
+    rc = lib.csp_solve_batch(ctx, k, ctypes.cast(probs, ctypes.c_void_p), ctypes.cast(res, ctypes.c_void_p),
+                             ctypes.cast(cnt, ctypes.c_void_p) if counters else None, _stream(stream))
+    _check(ctx, rc)
+    return list(res), (list(cnt) if counters else None)
 
 
 def csp_last_kernel_ms(ctx) -> float:

@@ -57,6 +57,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "csp.h"
 
@@ -77,20 +78,31 @@ constexpr unsigned SF_OVER = 1u << 30;
 constexpr unsigned SF_INVAL = 1u << 29;
 constexpr unsigned SF_MASK = 0x1FFFFFFFu;
 
+// Per-instance outputs of a range-owned solve.
+struct Out {
+    long long res[5];              // T X x Y F2
+    unsigned long long ctr[8];     // C U D E R P I
+    unsigned long long prof[8];    // wall-clock ticks per phase (range 0)
+    int status;
+    int pad[3];
+};
+
+// State of one combining barrier among the g workgroups of a gang; the
+// header is followed by g member slot lines and g flag lines (16 x u64 each).
+struct BarHdr {
+    unsigned grp[NGRP][32];        // group counters, one per 128-byte line
+    unsigned root[32];
+    unsigned long long gslot[NGRP][16];
+    int broken;
+    int pad[31];
+};
+
+__host__ __device__ inline size_t bar_bytes(unsigned g) { return sizeof(BarHdr) + (size_t)2 * g * 128; }
+
 struct Ctl {
     unsigned grp[NGRP][32];        // barrier group counters, one per 128-byte line
     unsigned root[32];
-    // reducing barrier: per-group and root accumulators (min, or, sum)
-    unsigned gmin[NGRP][32];
-    unsigned gor[NGRP][32];
-    unsigned long long gsum[NGRP][16];
-    unsigned rmin[32];
-    unsigned ror[32];
-    unsigned long long rsum[16];
     unsigned flag[GMAX][32];       // per-workgroup release flags
-    unsigned long long cslot[GMAX][16];   // combining barrier: member slots
-    unsigned long long gslot[NGRP][16];   // combining barrier: group slots
-    unsigned long long cflag[GMAX][16];   // combining barrier: epoch and result per workgroup
     unsigned qslot[GMAX];          // arrival: frontier size | flags
     unsigned nslot[GMAX];          // departure: next delta (0 = none) | flags
     unsigned tslot[GMAX];          // departure: flows in transit
@@ -104,6 +116,10 @@ struct Ctl {
     unsigned long long prof[8];    // wall-clock ticks per phase (workgroup 0)
     int status;
     int broken;
+    // range-owned solves
+    Out rout;
+    BarHdr rbar;
+    unsigned long long rbar_lines[2 * GMAX][16];
 };
 
 enum { ST_RUNNING = 0, ST_DONE = 1, ST_OVERFLOW = 2, ST_CANCELED = 3, ST_BROKEN = 4, ST_INVAL = 5 };
@@ -268,8 +284,6 @@ __global__ void __launch_bounds__(BLOCK) k_reset_ctl(Ctl *ctl)
     for (unsigned i = threadIdx.x; i < sizeof(Ctl) / 4; i += BLOCK) w[i] = 0;
     __syncthreads();
     if (threadIdx.x == 0) ctl->ydir = 0xFFFFFFFFu;
-    if (threadIdx.x < NGRP) ctl->gmin[threadIdx.x][0] = 0xFFFFFFFFu;
-    if (threadIdx.x == 0) ctl->rmin[0] = 0xFFFFFFFFu;
 }
 
 // Repack SoA edge arrays into per-vertex records of 2d (f1, f2) pairs in
@@ -731,82 +745,110 @@ struct Comb {
     unsigned long long mx;              // maximum
 };
 
-// Tree barrier over a cooperative grid that combines one Comb per
-// workgroup.  Members write their Comb to a private slot line, publish with
-// an agent-scope release fence and count themselves in their XCD group; the
-// group's last arriver combines the members' slots with one wavefront, writes
-// the group slot and counts the group at the root; the last group combines
-// the group slots and writes the result and the new epoch into every
-// workgroup's flag line.  Waits are bounded as in grid_sync.
-__device__ bool grid_combine(Ctl *ctl, unsigned &epoch, unsigned long long limit, const Comb &mine, Comb &out)
+__device__ __forceinline__ unsigned long long *bar_slot(BarHdr *b, unsigned i)
+{
+    return reinterpret_cast<unsigned long long *>(b + 1) + (size_t)i * 16;
+}
+
+__device__ __forceinline__ unsigned long long *bar_flag(BarHdr *b, unsigned g, unsigned i)
+{
+    return reinterpret_cast<unsigned long long *>(b + 1) + ((size_t)g + i) * 16;
+}
+
+__device__ __forceinline__ unsigned long long ld64(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st64(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void comb_wave(unsigned &mn, unsigned &orf, unsigned long long &s0,
+                                          unsigned long long &s1, unsigned long long &s2,
+                                          unsigned long long &mx)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = min(mn, (unsigned)__shfl_xor(mn, o));
+        orf |= __shfl_xor(orf, o);
+        s0 += __shfl_xor(s0, o);
+        s1 += __shfl_xor(s1, o);
+        s2 += __shfl_xor(s2, o);
+        const unsigned long long om = __shfl_xor(mx, o);
+        mx = om > mx ? om : mx;
+    }
+}
+
+// Tree barrier among the g workgroups of a gang (member m is the caller)
+// that combines one Comb per member.  Members write their Comb to a private
+// slot line, publish with an agent-scope release fence and count themselves
+// in group m % 8; the group's last arriver combines the group's slots with
+// one wavefront, writes the group slot and counts the group at the root; the
+// last group combines the group slots and writes the result, then the new
+// epoch, into every member's flag line.  Waiters spin on their own line; a
+// wait that outlasts `limit` wall-clock ticks marks the gang broken and the
+// call returns false, so a logic error drains the gang instead of hanging.
+__device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
+                             const Comb &mine, Comb &out)
 {
     __shared__ int s_ok;
-    __shared__ unsigned long long s_o[6];
+    __shared__ unsigned long long s_o[5];
     __syncthreads();
     ++epoch;
-    const unsigned G = gridDim.x;
-    if (G == 1) {
+    if (g == 1) {
         out = mine;
         return true;
     }
     if (threadIdx.x < 64) {
         const unsigned lane = threadIdx.x;
-        const unsigned grp = blockIdx.x % NGRP;
-        const unsigned ngrp = G < NGRP ? G : NGRP;
-        const unsigned members = (G - grp + NGRP - 1) / NGRP;
+        const unsigned grp = m % NGRP;
+        const unsigned ngrp = g < NGRP ? g : NGRP;
+        const unsigned members = (g - grp + NGRP - 1) / NGRP;
         int leader = 0;
         if (lane == 0) {
-            unsigned long long *sl = ctl->cslot[blockIdx.x];
-            __hip_atomic_store(&sl[0], (unsigned long long)mine.mn | ((unsigned long long)mine.orf << 32),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sl[1], mine.s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sl[2], mine.s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sl[3], mine.s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sl[4], mine.mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned long long *sl = bar_slot(bh, m);
+            st64(&sl[0], (unsigned long long)mine.mn | ((unsigned long long)mine.orf << 32));
+            st64(&sl[1], mine.s0);
+            st64(&sl[2], mine.s1);
+            st64(&sl[3], mine.s2);
+            st64(&sl[4], mine.mx);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const unsigned a = __hip_atomic_fetch_add(&ctl->grp[grp][0], 1u, __ATOMIC_RELAXED,
+            const unsigned a = __hip_atomic_fetch_add(&bh->grp[grp][0], 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             leader = a == members - 1;
-            if (leader) st_rlx(&ctl->grp[grp][0], 0u);
+            if (leader) st_rlx(&bh->grp[grp][0], 0u);
         }
         leader = __shfl(leader, 0);
         if (leader) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             unsigned mn = 0xFFFFFFFFu, orf = 0;
             unsigned long long s0 = 0, s1 = 0, s2 = 0, mx = 0;
-            if (lane < members) {
-                const unsigned long long *sl = ctl->cslot[grp + NGRP * lane];
-                const unsigned long long w0 = __hip_atomic_load(&sl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                mn = (unsigned)w0;
-                orf = (unsigned)(w0 >> 32);
-                s0 = __hip_atomic_load(&sl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s1 = __hip_atomic_load(&sl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s2 = __hip_atomic_load(&sl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                mx = __hip_atomic_load(&sl[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (unsigned j = lane; j < members; j += 64) {
+                const unsigned long long *sl = bar_slot(bh, grp + NGRP * j);
+                const unsigned long long w0 = ld64(&sl[0]);
+                mn = min(mn, (unsigned)w0);
+                orf |= (unsigned)(w0 >> 32);
+                s0 += ld64(&sl[1]);
+                s1 += ld64(&sl[2]);
+                s2 += ld64(&sl[3]);
+                const unsigned long long v = ld64(&sl[4]);
+                mx = v > mx ? v : mx;
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                mn = min(mn, (unsigned)__shfl_xor(mn, o));
-                orf |= __shfl_xor(orf, o);
-                s0 += __shfl_xor(s0, o);
-                s1 += __shfl_xor(s1, o);
-                s2 += __shfl_xor(s2, o);
-                const unsigned long long om = __shfl_xor(mx, o);
-                mx = om > mx ? om : mx;
-            }
+            comb_wave(mn, orf, s0, s1, s2, mx);
             int releaser = 0;
             if (lane == 0) {
-                unsigned long long *gs = ctl->gslot[grp];
-                __hip_atomic_store(&gs[0], (unsigned long long)mn | ((unsigned long long)orf << 32),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&gs[1], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&gs[2], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&gs[3], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&gs[4], mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                unsigned long long *gs = bh->gslot[grp];
+                st64(&gs[0], (unsigned long long)mn | ((unsigned long long)orf << 32));
+                st64(&gs[1], s0);
+                st64(&gs[2], s1);
+                st64(&gs[3], s2);
+                st64(&gs[4], mx);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                const unsigned rr = __hip_atomic_fetch_add(&ctl->root[0], 1u, __ATOMIC_RELAXED,
+                const unsigned rr = __hip_atomic_fetch_add(&bh->root[0], 1u, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);
                 releaser = rr == ngrp - 1;
-                if (releaser) st_rlx(&ctl->root[0], 0u);
+                if (releaser) st_rlx(&bh->root[0], 0u);
             }
             releaser = __shfl(releaser, 0);
             if (releaser) {
@@ -815,56 +857,44 @@ __device__ bool grid_combine(Ctl *ctl, unsigned &epoch, unsigned long long limit
                 orf = 0;
                 s0 = s1 = s2 = mx = 0;
                 if (lane < ngrp) {
-                    const unsigned long long *gs = ctl->gslot[lane];
-                    const unsigned long long w0 =
-                        __hip_atomic_load(&gs[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long *gs = bh->gslot[lane];
+                    const unsigned long long w0 = ld64(&gs[0]);
                     mn = (unsigned)w0;
                     orf = (unsigned)(w0 >> 32);
-                    s0 = __hip_atomic_load(&gs[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s1 = __hip_atomic_load(&gs[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s2 = __hip_atomic_load(&gs[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    mx = __hip_atomic_load(&gs[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s0 = ld64(&gs[1]);
+                    s1 = ld64(&gs[2]);
+                    s2 = ld64(&gs[3]);
+                    mx = ld64(&gs[4]);
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    mn = min(mn, (unsigned)__shfl_xor(mn, o));
-                    orf |= __shfl_xor(orf, o);
-                    s0 += __shfl_xor(s0, o);
-                    s1 += __shfl_xor(s1, o);
-                    s2 += __shfl_xor(s2, o);
-                    const unsigned long long om = __shfl_xor(mx, o);
-                    mx = om > mx ? om : mx;
-                }
+                comb_wave(mn, orf, s0, s1, s2, mx);
                 const unsigned long long w0 = (unsigned long long)mn | ((unsigned long long)orf << 32);
-                for (unsigned i = lane; i < G; i += 64) {
-                    unsigned long long *fl = ctl->cflag[i];
-                    __hip_atomic_store(&fl[1], w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&fl[2], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&fl[3], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&fl[4], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&fl[5], mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (unsigned i = lane; i < g; i += 64) {
+                    unsigned long long *fl = bar_flag(bh, g, i);
+                    st64(&fl[1], w0);
+                    st64(&fl[2], s0);
+                    st64(&fl[3], s1);
+                    st64(&fl[4], s2);
+                    st64(&fl[5], mx);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                for (unsigned i = lane; i < G; i += 64)
-                    __hip_atomic_store(&ctl->cflag[i][0], (unsigned long long)epoch, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], (unsigned long long)epoch);
             }
         }
         if (lane == 0) {
             int ok = 1;
-            unsigned long long *fl = ctl->cflag[blockIdx.x];
+            unsigned long long *fl = bar_flag(bh, g, m);
             const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(&fl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned long long)epoch) {
+            while (ld64(&fl[0]) < (unsigned long long)epoch) {
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > limit) {
-                    __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (__hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-            for (int k = 0; k < 5; ++k)
-                s_o[k] = __hip_atomic_load(&fl[1 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+            for (int k = 0; k < 5; ++k) s_o[k] = ld64(&fl[1 + k]);
             s_ok = ok;
         }
     }
@@ -880,24 +910,29 @@ __device__ bool grid_combine(Ctl *ctl, unsigned &epoch, unsigned long long limit
     return ok;
 }
 
-struct PR {
-    long long N;
+// One range-owned solve (a "job"): everything a gang of g workgroups needs.
+struct RJ {
+    long long n, N;
     long long off[8];              // neighbour offset per direction
     long long offq[8];             // floor(off / c)
     long long offr[8];             // off - c * floor(off / c), in [0, c)
     long long c;                   // vertices per range
+    int d;
     int K;                         // neighbours lie within K ranges
-    int xcd_map;                   // give each XCD a contiguous run of ranges
-    const void *rec;
+    int lt;                        // LDS label bytes (2 or 4)
+    unsigned g;                    // ranges (workgroups) in the gang
+    const uint8_t *f1, *f2;        // SoA edge arrays [d][N]
     const uint8_t *A, *B;
     unsigned M;
-    unsigned *lists;               // [G][c] frontier list per range
-    uint2 *pool;                   // [G][W][S] wheel of each range
-    unsigned long long pool_flows;
-    uint2 *cand;                   // [2][G][NO][cand_cap] candidates by sender and offset
     unsigned cand_cap;
-    unsigned *pubc;                // [2][G][NOMAX] candidate fills
-    Ctl *ctl;
+    void *rec;                     // packed edge records, written by the owners
+    unsigned *lists;               // [g][c] frontier list per range
+    uint2 *pool;                   // [g][W][S] wheel of each range
+    unsigned long long pool_flows;
+    uint2 *cand;                   // [2][g][NO][cand_cap] candidates by sender and offset
+    unsigned *pubc;                // [2][g][NOMAX] candidate fills
+    BarHdr *bar;
+    Out *out;
     unsigned *labels_out;
     long long max_cycles;
     unsigned long long wait_limit;
@@ -928,60 +963,92 @@ __device__ __forceinline__ bool lab_raise(uint16_t *lab, unsigned i, unsigned q)
     }
 }
 
-constexpr unsigned CAND_LI = 0x1FFFFu;     // candidate word 0: local index | f1 << 17 | dir << 25
+// LDS labels of a range are 16 or 32 bits wide (uniform per workgroup).
+__device__ __forceinline__ unsigned lget(const unsigned *lw, bool l16, unsigned i)
+{
+    return l16 ? (unsigned)reinterpret_cast<const uint16_t *>(lw)[i] : lw[i];
+}
 
-template <int D, typename LT>
-__global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
+__device__ __forceinline__ void lset(unsigned *lw, bool l16, unsigned i, unsigned v)
+{
+    if (l16) reinterpret_cast<uint16_t *>(lw)[i] = (uint16_t)v;
+    else lw[i] = v;
+}
+
+__device__ __forceinline__ bool lraise(unsigned *lw, bool l16, unsigned i, unsigned q)
+{
+    return l16 ? lab_raise(reinterpret_cast<uint16_t *>(lw), i, q) : lab_raise(lw, i, q);
+}
+
+constexpr unsigned CAND_LI = 0x1FFFFu;     // candidate word 0: local index | f1 << 17 | dir << 25
+constexpr unsigned SF_BAD = 1u << 28;      // an edge with f1 or f2 equal to 0
+
+// Range r of job p, run by the calling workgroup.  smem is the dynamic LDS
+// block: labels | frontier bitmap | B bitmap | wheel fills [MAXW].
+//
+// Initialisation (Algorithm 3) packs the range's edge records (per vertex,
+// (f1, f2) of its 2d edges in direction order, zero where the lattice ends),
+// checks the edges, sets labels (M on A) and the A and B bitmaps.  A first
+// barrier combines the largest f1 (it sizes the wheel) and input errors.
+// Then each cycle:
+//   departure (Steps 4-5) from I_t: inside the range, test and file flows;
+//     across ranges, ship candidates to the owning range
+//   barrier: next event time, flags, counts, best B key (Steps 1, 6)
+//   accept candidates shipped at t_prev against this range's labels
+//   arrival (Steps 1-3, 8): deliver bucket t, commit labels, build I_t
+template <int D>
+__device__ void range_run(const RJ &p, unsigned r, unsigned *smem)
 {
     using RT = typename Rec<D>::T;
-    extern __shared__ unsigned smem[];
     __shared__ unsigned s_wave[NWAVES];
     __shared__ unsigned s_flags;
     __shared__ unsigned s_min;
     __shared__ unsigned s_ydir;
+    __shared__ unsigned s_mf;
     __shared__ unsigned long long s_xkey;
     __shared__ unsigned long long s_sum;
     __shared__ unsigned long long s_red[4];
-    __shared__ unsigned s_ccnt[NOMAX];        // candidates shipped this cycle, by offset
-    __shared__ unsigned s_cpre[NOMAX + 1];    // incoming candidates, prefix by sender
+    __shared__ unsigned s_ccnt[NOMAX];        // candidates shipped / received this cycle
+    __shared__ unsigned s_cpre[NOMAX + 1];
 
-    Ctl *ctl = p.ctl;
     const unsigned tid = threadIdx.x, lane = lane_id();
-    const unsigned G = gridDim.x;
-    const unsigned r = (p.xcd_map && (G % NGRP) == 0) ? (blockIdx.x % NGRP) * (G / NGRP) + blockIdx.x / NGRP
-                                                      : blockIdx.x;
-    const bool lead = blockIdx.x == 0;
-    const long long N = p.N, c = p.c;
+    const unsigned G = p.g;
+    const bool lead = r == 0;
+    long long offq[2 * D], offr[2 * D], offv[2 * D];
+#pragma unroll
+    for (int dir = 0; dir < 2 * D; ++dir) {
+        offq[dir] = p.offq[dir];
+        offr[dir] = p.offr[dir];
+        offv[dir] = p.off[dir];
+    }
+    const long long n = p.n, N = p.N, c = p.c;
     const long long base = (long long)r * c;
     const unsigned cr = (unsigned)max(0ll, min(c, N - base));
     const int K = p.K, NO = 2 * K + 1;
-    const RT *rec = static_cast<const RT *>(p.rec);
+    RT *rec = static_cast<RT *>(p.rec);
+    Out *out = p.out;
     unsigned epoch = 0;
 
-    unsigned W = 2;
-    while (W <= ctl->maxf1) W <<= 1;
-    const unsigned Wm = W - 1;
-    const unsigned long long S = p.pool_flows / ((unsigned long long)G * W);
-    const unsigned CS = p.cand_cap;
-
-    // LDS: labels | frontier bitmap | B bitmap | wheel fills [MAXW]
     const unsigned cw = (unsigned)((c + 31) / 32);
-    const unsigned lab_words = (unsigned)((c * (long long)sizeof(LT) + 3) / 4);
-    LT *lab = reinterpret_cast<LT *>(smem);
+    const bool l16 = p.lt == 2;
+    const unsigned lab_words = (unsigned)((c * (long long)(l16 ? 2 : 4) + 3) / 4);
+    unsigned *lab = smem;
     unsigned *fb = smem + lab_words;
     unsigned *bb = fb + cw;
     unsigned *cnt = bb + cw;
     unsigned *mylist = p.lists + (unsigned long long)r * c;
-    uint2 *wheel = p.pool + (unsigned long long)r * W * S;
-    auto candbuf = [&](unsigned par, unsigned long long src, unsigned oi) {
-        return p.cand + (((unsigned long long)par * G + src) * NO + oi) * CS;
+    uint2 *const cand = p.cand;
+    unsigned *const pubc_base = p.pubc;
+    const unsigned long long ccap = p.cand_cap;
+    auto candbuf = [=](unsigned par, unsigned long long src, unsigned oi) {
+        return cand + (((unsigned long long)par * G + src) * NO + oi) * ccap;
     };
-    auto pubc = [&](unsigned par, unsigned long long src, unsigned oi) {
-        return p.pubc + ((unsigned long long)par * G + src) * NOMAX + oi;
+    auto pubc = [=](unsigned par, unsigned long long src, unsigned oi) {
+        return pubc_base + ((unsigned long long)par * G + src) * NOMAX + oi;
     };
 
     unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread, committed
-    unsigned long long cC = 0, cP = 0, cI = 0;              // every workgroup, from the barrier
+    unsigned long long cC = 0, cP = 0, cI = 0;              // every workgroup alike, from the barrier
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
     const bool timing = p.prof && lead && tid == 0;
 #define PHASE4(k)                                            \
@@ -999,29 +1066,81 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
         s_flags = 0;
         s_xkey = 0;
         s_ydir = 0xFFFFFFFFu;
+        s_mf = 0;
     }
     __syncthreads();
 
-    int status = ctl->bad ? ST_INVAL : ST_RUNNING;
-
-    // ---- Initialization (Algorithm 3): Label = M on A, 0 elsewhere; A is I_0.
-    if (status == ST_RUNNING) {
+    // ---- Initialization (Algorithm 3): pack and check the range's edges;
+    // Label = M on A, 0 elsewhere; A is I_0.
+    {
+        unsigned mf = 0, bad = 0;
+        long long stride[D];
+        {
+            long long sv = 1;
+            for (int k = 0; k < D; ++k) {
+                stride[k] = sv;
+                sv *= n;
+            }
+        }
         for (unsigned i = tid; i < cr; i += BLOCK) {
             const long long v = base + i;
+            long long cc[D];
+            long long rem = v;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                cc[k] = rem % n;
+                rem /= n;
+            }
+            unsigned pr[2 * D];
+#pragma unroll
+            for (int dir = 0; dir < 2 * D; ++dir) {
+                const bool lower = dir < D;
+                const int k = lower ? D - 1 - dir : dir - D;
+                const bool exists = lower ? (cc[k] >= 1) : (cc[k] <= n - 2);
+                pr[dir] = 0;
+                if (exists) {
+                    const long long e = (long long)k * N + (lower ? v - stride[k] : v);
+                    const unsigned a = p.f1[e], b = p.f2[e];
+                    if (a == 0 || b == 0) bad = 1;
+                    mf = a > mf ? a : mf;
+                    pr[dir] = a | (b << 8);
+                }
+            }
+            RT rv;
+            if constexpr (D == 1) {
+                rv = pr[0] | (pr[1] << 16);
+            } else if constexpr (D == 2) {
+                rv = make_uint2(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16));
+            } else if constexpr (D == 3) {
+                rv = make_uint4(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16), pr[4] | (pr[5] << 16), 0u);
+            } else {
+                rv = make_uint4(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16), pr[4] | (pr[5] << 16),
+                                pr[6] | (pr[7] << 16));
+            }
+            rec[v] = rv;
             const bool a = p.A[v] != 0, b = p.B[v] != 0;
-            if (a && b) atomicOr(&s_flags, SF_INVAL);
+            if (a && b) bad |= 2;
             if (a) {
-                lab[i] = (LT)p.M;
+                lset(lab, l16, i, p.M);
                 atomicOr(&fb[i >> 5], 1u << (i & 31));
             }
             if (b) atomicOr(&bb[i >> 5], 1u << (i & 31));
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mf = max(mf, (unsigned)__shfl_xor(mf, o));
+            bad |= __shfl_xor(bad, o);
+        }
+        if (lane == 0) {
+            if (mf) atomicMax(&s_mf, mf);
+            if (bad & 1) atomicOr(&s_flags, SF_BAD);
+            if (bad & 2) atomicOr(&s_flags, SF_INVAL);
         }
     }
     __syncthreads();
 
     // Frontier bitmap -> sorted list of local indices; clear the bitmap;
     // best (label, -index) over the B members in it.
-    auto compact = [&]() -> unsigned {
+    auto compact = [=]() -> unsigned {
         unsigned total = 0;
         unsigned long long bestB = 0;
         for (unsigned w0 = 0; w0 < cw; w0 += BLOCK) {
@@ -1041,7 +1160,7 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
                 const unsigned i = wi * 32u + bt;
                 mylist[k++] = i;
                 if ((bm >> bt) & 1u) {
-                    const unsigned long long key = ((unsigned long long)lab_get(lab, i) << 32) |
+                    const unsigned long long key = ((unsigned long long)lget(lab, l16, i) << 32) |
                                                    (0xFFFFFFFFull - (unsigned long long)(base + i));
                     bestB = key > bestB ? key : bestB;
                 }
@@ -1060,11 +1179,27 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
         return total;
     };
 
-    unsigned nlist = 0;
-    if (status == ST_RUNNING) {
-        nlist = compact();
-        if (tid == 0) cU += nlist;
+    unsigned nlist = compact();
+    if (tid == 0) cU += nlist;
+
+    int status = ST_RUNNING;
+    unsigned W = 2;
+    {
+        Comb mine, all;
+        mine.mn = 0xFFFFFFFFu;
+        mine.orf = s_flags & (SF_BAD | SF_INVAL);
+        mine.s0 = mine.s1 = mine.s2 = 0;
+        mine.mx = s_mf;
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all)) status = ST_BROKEN;
+        else if (all.orf & (SF_BAD | SF_INVAL)) status = ST_INVAL;
+        while (W <= (unsigned)all.mx) W <<= 1;
+        if (tid == 0) s_flags = 0;                   // an A member of B is an error, not a hit
+        __syncthreads();
     }
+    const unsigned Wm = W - 1;
+    const unsigned long long S = p.pool_flows / ((unsigned long long)G * W);
+    const unsigned CS = p.cand_cap;
+    uint2 *wheel = p.pool + (unsigned long long)r * W * S;
 
     long long t = 0, t_prev = 0;
     unsigned cyc = 0, par = 0;
@@ -1082,7 +1217,7 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
         for (unsigned j = tid; j < nlist; j += BLOCK) {
             const unsigned i = mylist[j];
             const long long Q = base + i;
-            const unsigned L = lab_get(lab, i);
+            const unsigned L = lget(lab, l16, i);
             const RT rv = rec[Q];
 #pragma unroll
             for (int dir = 0; dir < 2 * D; ++dir) {
@@ -1092,12 +1227,12 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
                 ++dD;
                 const int q = (int)L - (int)a2;
                 if (q <= 0) continue;
-                const long long lo = (long long)i + p.offr[dir];
-                const int o = (int)p.offq[dir] + (lo >= c ? 1 : 0);
+                const long long lo = (long long)i + offr[dir];
+                const int o = (int)offq[dir] + (lo >= c ? 1 : 0);
                 const unsigned li = (unsigned)(lo >= c ? lo - c : lo);   // index in the owner's range
                 const unsigned rdir = (unsigned)(2 * D - 1 - dir);      // sender seen from the receiver
                 if (o == 0) {
-                    if ((unsigned)q > lab_get(lab, li)) {
+                    if ((unsigned)q > lget(lab, l16, li)) {
                         const unsigned bk = (unsigned)((t + a1) & Wm);
                         const unsigned pos = atomicAdd(&cnt[bk], 1u);
                         if (pos < S)
@@ -1148,15 +1283,14 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
         PHASE4(0);
         Comb mine, all;
         mine.mn = s_min;
-        mine.orf = s_flags & (SF_OVER | SF_BHIT | SF_INVAL);
+        mine.orf = s_flags & (SF_OVER | SF_BHIT);
         mine.s0 = F;
         mine.s1 = nlist;
         mine.s2 = transit;
         mine.mx = s_xkey;
-        if (!grid_combine(ctl, epoch, p.wait_limit, mine, all)) { status = ST_BROKEN; break; }
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all)) { status = ST_BROKEN; break; }
         PHASE4(1);
 
-        if (all.orf & SF_INVAL) { status = ST_INVAL; break; }          // A and B overlap
         if (all.orf & SF_OVER) { status = ST_OVERFLOW; break; }
         if (cyc > 0) {
             cC += all.s0 > 0 ? 1 : 0;
@@ -1177,18 +1311,24 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
                     if (f.x == X && (f.y >> 3) == LX) atomicMin(&s_ydir, f.y & 7u);
                 }
                 __syncthreads();
-                if (tid == 0 && s_ydir >= 2u * D) {
-                    __hip_atomic_store(&ctl->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } else if (tid == 0) {
+                if (tid == 0) {
                     const unsigned yd = s_ydir;
-                    const long long Y = (long long)X + p.off[yd];
-                    const bool lower = (int)yd < D;
-                    const int k = lower ? D - 1 - (int)yd : (int)yd - D;
-                    ctl->res[0] = t;
-                    ctl->res[1] = X;
-                    ctl->res[2] = (long long)k * N + (lower ? Y : (long long)X);
-                    ctl->res[3] = Y;
-                    ctl->res[4] = (long long)p.M - (long long)LX;
+                    if (yd >= 2u * D) {
+                        __hip_atomic_store(&p.bar->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        long long oy = 0;
+#pragma unroll
+                        for (int dd = 0; dd < 2 * D; ++dd)
+                            if ((unsigned)dd == yd) oy = offv[dd];
+                        const long long Y = (long long)X + oy;
+                        const bool lower = (int)yd < D;
+                        const int k = lower ? D - 1 - (int)yd : (int)yd - D;
+                        out->res[0] = t;
+                        out->res[1] = X;
+                        out->res[2] = (long long)k * N + (lower ? Y : (long long)X);
+                        out->res[3] = Y;
+                        out->res[4] = (long long)p.M - (long long)LX;
+                    }
                 }
             }
             status = ST_DONE;
@@ -1227,7 +1367,7 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
                 const long long src = (long long)r + (oi - K);
                 const uint2 cd = candbuf(par, (unsigned long long)src, (unsigned)(2 * K - oi))[j - s_cpre[oi]];
                 const unsigned li = cd.x & CAND_LI, a1 = (cd.x >> 17) & 0xFFu, rdir = cd.x >> 25;
-                if (cd.y > lab_get(lab, li)) {
+                if (cd.y > lget(lab, l16, li)) {
                     const unsigned bk = (unsigned)((t_prev + a1) & Wm);
                     const unsigned pos = atomicAdd(&cnt[bk], 1u);
                     if (pos < S)
@@ -1258,13 +1398,12 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
             for (unsigned j = tid; j < F; j += BLOCK) {
                 const uint2 f = bkt[j];
                 const unsigned i = (unsigned)((long long)f.x - base);
-                if (lab_raise(lab, i, f.y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
+                if (lraise(lab, l16, i, f.y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
             }
             if (tid == 0) cR += F;
             __syncthreads();
             if (tid == 0) {
                 cnt[bk] = 0;
-                transit = s_sum;
                 s_flags &= SF_OVER;
                 s_xkey = 0;
             }
@@ -1280,7 +1419,7 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
 
     // ---- outputs
     if (status == ST_DONE && p.labels_out) {
-        for (unsigned i = tid; i < cr; i += BLOCK) p.labels_out[base + i] = lab_get(lab, i);
+        for (unsigned i = tid; i < cr; i += BLOCK) p.labels_out[base + i] = lget(lab, l16, i);
     }
     __syncthreads();
     if (tid == 0) {
@@ -1293,25 +1432,77 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(PR p)
     if (cR) atomicAdd(&s_red[3], cR);
     __syncthreads();
     if (tid == 0) {
-        if (s_red[0]) atomicAdd(&ctl->ctr[1], s_red[0]);
-        if (s_red[1]) atomicAdd(&ctl->ctr[2], s_red[1]);
-        if (s_red[2]) atomicAdd(&ctl->ctr[3], s_red[2]);
-        if (s_red[3]) atomicAdd(&ctl->ctr[4], s_red[3]);
+        if (s_red[0]) atomicAdd(&out->ctr[1], s_red[0]);
+        if (s_red[1]) atomicAdd(&out->ctr[2], s_red[1]);
+        if (s_red[2]) atomicAdd(&out->ctr[3], s_red[2]);
+        if (s_red[3]) atomicAdd(&out->ctr[4], s_red[3]);
         if (lead) {
-            for (int i = 0; i < 6; ++i) ctl->prof[i] = ph[i];
-            ctl->ctr[0] = cC;
-            ctl->ctr[5] = cP;
-            ctl->ctr[6] = cI;
-            const int br = __hip_atomic_load(&ctl->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ctl->status = br ? ST_BROKEN : status;
+            for (int i = 0; i < 6; ++i) out->prof[i] = ph[i];
+            out->ctr[0] = cC;
+            out->ctr[5] = cP;
+            out->ctr[6] = cI;
+            const int br = __hip_atomic_load(&p.bar->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            out->status = br ? ST_BROKEN : status;
             if (status == ST_DONE && !found) {
-                for (int i = 0; i < 5; ++i) ctl->res[i] = -1;
+                for (int i = 0; i < 5; ++i) out->res[i] = -1;
             }
         }
+    }
+    __syncthreads();
+}
+
+// Single solve: the whole grid is one gang; range r of physical block b is
+// chosen so that each XCD (blocks b = x mod 8) holds a contiguous run.
+template <int D>
+__global__ void __launch_bounds__(BLOCK) k_ranges(RJ p)
+{
+    extern __shared__ unsigned smem[];
+    const unsigned G = gridDim.x;
+    const unsigned r = (G % NGRP) == 0 ? (blockIdx.x % NGRP) * (G / NGRP) + blockIdx.x / NGRP : blockIdx.x;
+    range_run<D>(p, r, smem);
+}
+
+// Batched solves in one persistent launch.  Work is a list of (job, range)
+// slots ordered so that each job's ranges are consecutive and large jobs
+// come first; a workgroup takes the next slot with one atomic and runs that
+// range, meeting the rest of the job's gang at its barriers.  Every slot of
+// a gang is taken by a workgroup that finishes its earlier slots without
+// waiting on later ones, so every gang completes.
+struct BatchArgs {
+    const RJ *jobs;
+    const unsigned *slot_job;
+    const unsigned *slot_range;
+    unsigned nslots;
+    unsigned *next;                // slot counter
+};
+
+template <int D>
+__global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a)
+{
+    extern __shared__ unsigned smem[];
+    __shared__ unsigned s_slot;
+    for (;;) {
+        if (threadIdx.x == 0) s_slot = atomicAdd(a.next, 1u);
+        __syncthreads();
+        const unsigned sl = __builtin_amdgcn_readfirstlane(s_slot);
+        __syncthreads();
+        if (sl >= a.nslots) break;
+        const unsigned jb = __builtin_amdgcn_readfirstlane(a.slot_job[sl]);
+        const unsigned r = __builtin_amdgcn_readfirstlane(a.slot_range[sl]);
+        range_run<D>(a.jobs[jb], r, smem);
     }
 }
 
 __global__ void k_set_byte(uint8_t *p, long long i, uint8_t v) { p[i] = v; }
+
+// Zero `words` 32-bit words (a kernel rather than a memset, so the sequence
+// stays valid inside captured graphs).
+__global__ void __launch_bounds__(256) k_zero(unsigned *p, unsigned long long words)
+{
+    const unsigned long long gs = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gs)
+        p[i] = 0;
+}
 
 size_t rec_bytes(int d) { return d == 1 ? 4 : (d == 2 ? 8 : 16); }
 
@@ -1354,6 +1545,10 @@ struct csp_ctx {
     size_t cand_cap = 0;
     unsigned long long cand_seen = 0;
     unsigned long long pool_flows_seen = 0;   // largest pool a solve needed so far
+    uint8_t *arena = nullptr;       // batch: per-problem device state
+    size_t arena_cap = 0;
+    uint8_t *h_stage = nullptr;     // batch: pinned staging for job tables and results
+    size_t h_stage_cap = 0;
     char err[256] = {0};
 };
 
@@ -1391,19 +1586,22 @@ int grow(csp_ctx *ctx, T **p, size_t &cap, size_t need, const char *what)
 
 const void *lds_kernel(int d, int lt)
 {
-    if (lt == 2) {
-        switch (d) {
-        case 1: return (const void *)k_ranges<1, uint16_t>;
-        case 2: return (const void *)k_ranges<2, uint16_t>;
-        case 3: return (const void *)k_ranges<3, uint16_t>;
-        default: return (const void *)k_ranges<4, uint16_t>;
-        }
-    }
+    (void)lt;
     switch (d) {
-    case 1: return (const void *)k_ranges<1, unsigned>;
-    case 2: return (const void *)k_ranges<2, unsigned>;
-    case 3: return (const void *)k_ranges<3, unsigned>;
-    default: return (const void *)k_ranges<4, unsigned>;
+    case 1: return (const void *)k_ranges<1>;
+    case 2: return (const void *)k_ranges<2>;
+    case 3: return (const void *)k_ranges<3>;
+    default: return (const void *)k_ranges<4>;
+    }
+}
+
+const void *batch_kernel(int d)
+{
+    switch (d) {
+    case 1: return (const void *)k_batch<1>;
+    case 2: return (const void *)k_batch<2>;
+    case 3: return (const void *)k_batch<3>;
+    default: return (const void *)k_batch<4>;
     }
 }
 
@@ -1468,7 +1666,7 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
     LdsPlan pl;
     long long smax = 1;
     for (int k = 1; k < d; ++k) smax *= n;           // largest neighbour offset
-    const size_t budget = ctx->lds_limit > 2048 ? ctx->lds_limit - 2048 : 0;   // static LDS margin
+    const size_t budget = ctx->lds_limit > 4096 ? ctx->lds_limit - 4096 : 0;   // static LDS margin
     for (int G = std::max(1, G_want); G >= 1; G = (G > 1 ? G / 2 : 0)) {
         const long long c = (N + G - 1) / G;
         if ((long long)(G - 1) * c >= N) continue;    // empty range
@@ -1490,6 +1688,30 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
         if (G == 1) break;
     }
     return pl;
+}
+
+void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const long long off[8],
+              const uint8_t *f1, const uint8_t *f2, const uint8_t *A, const uint8_t *B, uint32_t M)
+{
+    memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.N = N;
+    p.c = plan.c;
+    p.d = d;
+    p.K = plan.K;
+    p.lt = plan.lt;
+    p.g = (unsigned)plan.G;
+    for (int dir = 0; dir < 8; ++dir) {
+        p.off[dir] = off[dir];
+        const long long q = off[dir] >= 0 ? off[dir] / plan.c : -((-off[dir] + plan.c - 1) / plan.c);
+        p.offq[dir] = q;
+        p.offr[dir] = off[dir] - q * plan.c;
+    }
+    p.f1 = f1;
+    p.f2 = f2;
+    p.A = A;
+    p.B = B;
+    p.M = M;
 }
 
 void launch_pack(int d, long long n, long long N, const uint8_t *f1, const uint8_t *f2, void *rec, Ctl *ctl,
@@ -1548,8 +1770,10 @@ void csp_destroy(csp_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     for (void *p : {(void *)ctx->lab, (void *)ctx->rec, (void *)ctx->queue, (void *)ctx->pool,
-                    (void *)ctx->ctl, (void *)ctx->in_buf, (void *)ctx->pub, (void *)ctx->cand})
+                    (void *)ctx->ctl, (void *)ctx->in_buf, (void *)ctx->pub, (void *)ctx->cand,
+                    (void *)ctx->arena})
         if (p) (void)hipFree(p);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     for (void *p : {(void *)ctx->h_ctl, (void *)ctx->h_byte})
         if (p) (void)hipHostFree(p);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -1629,8 +1853,6 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         rc = grow(ctx, &ctx->pool, ctx->pool_cap, (size_t)pool, "transit pool");
         if (rc) return rc;
         hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(BLOCK), 0, s, ctx->ctl);
-        launch_pack(d, n, N, f1, f2, ctx->rec, ctx->ctl, ctx->num_cu, s);
-        HIP_TRY(hipGetLastError(), "pack launch");
         if (use_lds) {
             rc = grow(ctx, &ctx->queue, ctx->queue_cap, (size_t)(plan.c * G), "frontier");
             if (rc) return rc;
@@ -1638,29 +1860,17 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             if (rc) return rc;
             rc = grow(ctx, &ctx->cand, ctx->cand_cap, (size_t)(2ull * G * NO * ccap), "candidates");
             if (rc) return rc;
-            PR p;
-            memset(&p, 0, sizeof(p));
-            p.N = N;
-            p.c = plan.c;
-            for (int dir = 0; dir < 8; ++dir) {
-                p.off[dir] = off[dir];
-                long long q = off[dir] >= 0 ? off[dir] / plan.c : -((-off[dir] + plan.c - 1) / plan.c);
-                p.offq[dir] = q;
-                p.offr[dir] = off[dir] - q * plan.c;
-            }
-            p.K = plan.K;
-            p.xcd_map = 1;
+            RJ p;
+            fill_job(p, d, n, N, plan, off, f1, f2, A, B, M);
             p.rec = ctx->rec;
-            p.A = A;
-            p.B = B;
-            p.M = M;
             p.lists = ctx->queue;
             p.pool = ctx->pool;
             p.pool_flows = pool;
             p.cand = ctx->cand;
             p.cand_cap = (unsigned)ccap;
             p.pubc = ctx->pub;
-            p.ctl = ctx->ctl;
+            p.bar = &ctx->ctl->rbar;
+            p.out = &ctx->ctl->rout;
             p.labels_out = labels;
             p.max_cycles = max_cycles;
             p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
@@ -1672,6 +1882,8 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
                     "solve launch");
             HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
         } else {
+            launch_pack(d, n, N, f1, f2, ctx->rec, ctx->ctl, ctx->num_cu, s);
+            HIP_TRY(hipGetLastError(), "pack launch");
             rc = grow(ctx, &ctx->queue, ctx->queue_cap, (size_t)(qs * G), "frontier");
             if (rc) return rc;
             Params p;
@@ -1700,10 +1912,14 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         HIP_TRY(hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "ctl copy");
         HIP_TRY(hipStreamSynchronize(s), "solve");
         const Ctl &c = *ctx->h_ctl;
-        if (c.status == ST_INVAL || c.bad) {
-            return fail(ctx, CSP_EINVAL, c.bad ? "an edge has f1 or f2 equal to 0" : "A and B overlap");
+        const int status = use_lds ? c.rout.status : c.status;
+        const long long *res = use_lds ? c.rout.res : c.res;
+        const unsigned long long *ctr = use_lds ? c.rout.ctr : c.ctr;
+        const unsigned long long *prof = use_lds ? c.rout.prof : c.prof;
+        if (status == ST_INVAL || (!use_lds && c.bad)) {
+            return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0, or A and B overlap");
         }
-        if (c.status == ST_OVERFLOW) {
+        if (status == ST_OVERFLOW) {
             if (pool >= pool_max && ccap >= cand_max)
                 return fail(ctx, CSP_EOVERFLOW, "transit pool overflow at the edge bound");
             pool = std::min(pool * 2, pool_max);
@@ -1711,28 +1927,28 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             ccap = std::min(ccap * 2, cand_max);
             continue;
         }
-        if (c.status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
-        if (c.status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out or inconsistent result");
-        if (c.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "solve did not finish");
+        if (status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
+        if (status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out or inconsistent result");
+        if (status != ST_DONE) return fail(ctx, CSP_EDEVICE, "solve did not finish");
         if (!ctx->pool_hint) {
             ctx->pool_flows_seen = std::max(ctx->pool_flows_seen, pool);
             ctx->cand_seen = std::max(ctx->cand_seen, ccap);
         }
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
-        for (int i = 0; i < 8; ++i) ctx->last_prof[i] = c.prof[i];
-        out->T = c.res[0];
-        out->X = c.res[1];
-        out->x = c.res[2];
-        out->Y = c.res[3];
-        out->F2 = c.res[4];
+        for (int i = 0; i < 8; ++i) ctx->last_prof[i] = prof[i];
+        out->T = res[0];
+        out->X = res[1];
+        out->x = res[2];
+        out->Y = res[3];
+        out->F2 = res[4];
         if (cnt) {
-            cnt->C = (int64_t)c.ctr[0];
-            cnt->U = (int64_t)c.ctr[1];
-            cnt->D = (int64_t)c.ctr[2];
-            cnt->E = (int64_t)c.ctr[3];
-            cnt->R = (int64_t)c.ctr[4];
-            cnt->P = (int64_t)c.ctr[5];
-            cnt->I = (int64_t)c.ctr[6];
+            cnt->C = (int64_t)ctr[0];
+            cnt->U = (int64_t)ctr[1];
+            cnt->D = (int64_t)ctr[2];
+            cnt->E = (int64_t)ctr[3];
+            cnt->R = (int64_t)ctr[4];
+            cnt->P = (int64_t)ctr[5];
+            cnt->I = (int64_t)ctr[6];
         }
         return CSP_OK;
     }
@@ -1836,6 +2052,249 @@ int csp_last_phase_us(const csp_ctx *ctx, double *us)
 {
     if (!ctx || !us) return CSP_EINVAL;
     for (int i = 0; i < 6; ++i) us[i] = (double)ctx->last_prof[i] * 1000.0 / (double)ctx->wall_khz;
+    return CSP_OK;
+}
+
+int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_result *out, csp_counters *cnt,
+                    void *stream)
+{
+    if (!ctx || count < 0 || (count > 0 && (!probs || !out))) return fail(ctx, CSP_EINVAL, "null argument");
+    if (count == 0) return CSP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t budget = ctx->lds_limit > 4096 ? ctx->lds_limit - 4096 : 0;
+
+    struct Plan {
+        long long N, c;
+        int g, K, lt;
+        size_t lds;
+        unsigned long long pool, ccap;
+        size_t off_rec, off_lists, off_pool, off_cand, off_pubc, off_bar, off_out, end;
+        long long off[8];
+    };
+    std::vector<Plan> plan(count);
+    std::vector<int> todo(count);
+    for (int i = 0; i < count; ++i) {
+        const csp_problem &q = probs[i];
+        if (!q.f1 || !q.f2 || !q.A || !q.B) return fail(ctx, CSP_EINVAL, "null argument in batch");
+        long long N = 0;
+        int rc = check_shape(ctx, q.d, q.n, q.M, N);
+        if (rc) return rc;
+        Plan &pl = plan[i];
+        pl.N = N;
+        long long stride[4] = {1, 1, 1, 1};
+        for (int k = 1; k < q.d; ++k) stride[k] = stride[k - 1] * q.n;
+        for (int dir = 0; dir < 8; ++dir) pl.off[dir] = 0;
+        for (int dir = 0; dir < 2 * q.d; ++dir) {
+            const bool lower = dir < q.d;
+            const int k = lower ? q.d - 1 - dir : dir - q.d;
+            pl.off[dir] = lower ? -stride[k] : stride[k];
+        }
+        // 16-bit labels when M allows (larger ranges, fewer workgroups per gang)
+        pl.lt = q.M <= 0xFFFFu ? 2 : 4;
+        long long cmax = 0;
+        {
+            long long lo = 1, hi = 1ll << 22;
+            while (lo < hi) {
+                const long long mid = (lo + hi + 1) / 2;
+                if (lds_bytes_for(mid, 0, pl.lt) <= budget) lo = mid;
+                else hi = mid - 1;
+            }
+            cmax = lo;
+        }
+        pl.g = (int)std::min<long long>((N + cmax - 1) / cmax, std::min(ctx->num_cu, GMAX));
+        pl.c = (N + pl.g - 1) / pl.g;
+        if (pl.c > cmax) return fail(ctx, CSP_EINVAL, "batch problem too large for one launch");
+        long long smax = stride[q.d - 1];
+        pl.K = pl.g == 1 ? 0 : (int)((smax + pl.c - 1) / pl.c);
+        if (pl.K > KMAX) return fail(ctx, CSP_EINVAL, "batch problem ranges too thin");
+        pl.lds = lds_bytes_for(pl.c, pl.K, pl.lt);
+        pl.pool = ctx->pool_hint ? ctx->pool_hint * 256ull * pl.g
+                                 : std::max<unsigned long long>(1ull << 15, 6ull * q.d * N);
+        const unsigned long long cmaxc = 2ull * q.d * (unsigned long long)pl.c;
+        pl.ccap = pl.g == 1 ? 1
+                            : std::min<unsigned long long>(cmaxc, ctx->pool_hint ? 64ull
+                                                                                 : std::max<unsigned long long>(
+                                                                                       2048, pl.c / 2));
+        todo[i] = i;
+    }
+
+    float total_ms = 0.f;
+    int rounds = 0;
+    while (!todo.empty()) {
+        if (++rounds > 24) return fail(ctx, CSP_EOVERFLOW, "batch did not converge");
+        // arena layout for the problems of this round
+        auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t at = 0;
+        for (int i : todo) {
+            Plan &pl = plan[i];
+            const int d = probs[i].d;
+            const long long NO = 2 * pl.K + 1;
+            pl.off_rec = at;
+            at = up(at + (size_t)pl.N * rec_bytes(d));
+            pl.off_lists = at;
+            at = up(at + (size_t)pl.g * pl.c * 4);
+            pl.off_pool = at;
+            at = up(at + (size_t)pl.pool * 8);
+            pl.off_cand = at;
+            at = up(at + (size_t)(2ull * pl.g * NO * pl.ccap * 8));
+            pl.off_pubc = at;
+            at = up(at + (size_t)2 * pl.g * NOMAX * 4);
+            pl.off_bar = at;
+            at = up(at + bar_bytes((unsigned)pl.g));
+            pl.off_out = at;
+            at = up(at + sizeof(Out));
+            pl.end = at;
+        }
+        const size_t n_todo = todo.size();
+        const size_t jobs_off = up(at), slots_off = up(jobs_off + n_todo * sizeof(RJ));
+        size_t nslots = 0;
+        for (int i : todo) nslots += (size_t)plan[i].g;
+        const size_t next_off = up(slots_off + 2 * nslots * 4);
+        const size_t total = next_off + 256;
+        int rc = grow(ctx, &ctx->arena, ctx->arena_cap, total, "batch arena");
+        if (rc) return rc;
+        const size_t stage = std::max(total - jobs_off, n_todo * sizeof(Out));
+        if (stage > ctx->h_stage_cap) {
+            if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+            ctx->h_stage = nullptr;
+            ctx->h_stage_cap = 0;
+            if (hipHostMalloc((void **)&ctx->h_stage, stage, hipHostMallocDefault) != hipSuccess)
+                return fail(ctx, CSP_ENOMEM, "batch staging");
+            ctx->h_stage_cap = stage;
+        }
+        // per-dimension groups, largest gangs first
+        std::vector<int> order(todo.begin(), todo.end());
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            if (probs[a].d != probs[b].d) return probs[a].d < probs[b].d;
+            if (plan[a].g != plan[b].g) return plan[a].g > plan[b].g;
+            return plan[a].N > plan[b].N;
+        });
+        uint8_t *h = ctx->h_stage;
+        RJ *hjobs = reinterpret_cast<RJ *>(h);
+        unsigned *hslot = reinterpret_cast<unsigned *>(h + (slots_off - jobs_off));
+        std::vector<size_t> job_of(count);
+        for (size_t j = 0; j < n_todo; ++j) {
+            const int i = order[j];
+            const csp_problem &q = probs[i];
+            const Plan &pl = plan[i];
+            LdsPlan lp;
+            lp.ok = true;
+            lp.G = pl.g;
+            lp.c = pl.c;
+            lp.K = pl.K;
+            lp.lt = pl.lt;
+            lp.lds = pl.lds;
+            RJ &p = hjobs[j];
+            fill_job(p, q.d, q.n, pl.N, lp, pl.off, q.f1, q.f2, q.A, q.B, q.M);
+            p.rec = ctx->arena + pl.off_rec;
+            p.lists = reinterpret_cast<unsigned *>(ctx->arena + pl.off_lists);
+            p.pool = reinterpret_cast<uint2 *>(ctx->arena + pl.off_pool);
+            p.pool_flows = pl.pool;
+            p.cand = reinterpret_cast<uint2 *>(ctx->arena + pl.off_cand);
+            p.cand_cap = (unsigned)pl.ccap;
+            p.pubc = reinterpret_cast<unsigned *>(ctx->arena + pl.off_pubc);
+            p.bar = reinterpret_cast<BarHdr *>(ctx->arena + pl.off_bar);
+            p.out = reinterpret_cast<Out *>(ctx->arena + pl.off_out);
+            p.labels_out = q.labels;
+            p.max_cycles = 0;
+            p.wait_limit = ctx->wall_khz * 1000ull * 60ull;   // 60 s
+            p.prof = 0;
+            job_of[i] = j;
+        }
+        // slot lists (job, range), grouped by dimension
+        std::vector<std::pair<int, std::pair<size_t, size_t>>> groups;   // d, [slot begin, end)
+        size_t sl = 0;
+        for (size_t j = 0; j < n_todo;) {
+            const int d = probs[order[j]].d;
+            const size_t b0 = sl;
+            while (j < n_todo && probs[order[j]].d == d) {
+                for (int m = 0; m < plan[order[j]].g; ++m) {
+                    hslot[sl] = (unsigned)j;
+                    hslot[nslots + sl] = (unsigned)m;
+                    ++sl;
+                }
+                ++j;
+            }
+            groups.push_back({d, {b0, sl}});
+        }
+        // zero barrier headers/lines and outputs, then upload the tables
+        for (int i : todo) {
+            const Plan &pl = plan[i];
+            const unsigned long long words = (pl.end - pl.off_bar) / 4;
+            const int nb = (int)std::max(1ull, std::min((words + 255) / 256, 1024ull));
+            hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s,
+                               reinterpret_cast<unsigned *>(ctx->arena + pl.off_bar), words);
+        }
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, reinterpret_cast<unsigned *>(ctx->arena + next_off),
+                           64ull);
+        HIP_TRY(hipGetLastError(), "batch zero");
+        HIP_TRY(hipMemcpyAsync(ctx->arena + jobs_off, h, next_off - jobs_off, hipMemcpyHostToDevice, s),
+                "batch tables");
+        HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
+        unsigned gi = 0;
+        for (auto &gr : groups) {
+            const int d = gr.first;
+            size_t lds = 0;
+            for (size_t q = gr.second.first; q < gr.second.second; ++q)
+                lds = std::max(lds, plan[order[hslot[q]]].lds);
+            const void *kf = batch_kernel(d);
+            if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                return fail(ctx, CSP_EDEVICE, "batch LDS attribute");
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kf, BLOCK, lds) != hipSuccess || nb < 1)
+                return fail(ctx, CSP_EDEVICE, "batch occupancy");
+            BatchArgs a;
+            a.jobs = reinterpret_cast<const RJ *>(ctx->arena + jobs_off);
+            a.slot_job = reinterpret_cast<const unsigned *>(ctx->arena + slots_off) + gr.second.first;
+            a.slot_range = reinterpret_cast<const unsigned *>(ctx->arena + slots_off) + nslots + gr.second.first;
+            a.nslots = (unsigned)(gr.second.second - gr.second.first);
+            a.next = reinterpret_cast<unsigned *>(ctx->arena + next_off) + gi++;
+            const int grid = std::min<int>(nb * ctx->num_cu, (int)a.nslots);
+            void *args[] = {&a};
+            HIP_TRY(hipLaunchCooperativeKernel(kf, dim3(grid), dim3(BLOCK), args, (unsigned)lds, s), "batch launch");
+        }
+        HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
+        // gather outputs
+        Out *hout = reinterpret_cast<Out *>(h);
+        for (size_t j = 0; j < n_todo; ++j)
+            HIP_TRY(hipMemcpyAsync(&hout[j], ctx->arena + plan[order[j]].off_out, sizeof(Out), hipMemcpyDeviceToHost,
+                                   s),
+                    "batch results");
+        HIP_TRY(hipStreamSynchronize(s), "batch");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "event time");
+        total_ms += ms;
+        std::vector<int> again;
+        for (size_t j = 0; j < n_todo; ++j) {
+            const int i = order[j];
+            const Out &o = hout[j];
+            if (o.status == ST_OVERFLOW) {
+                plan[i].pool *= 2;
+                plan[i].ccap = std::min<unsigned long long>(plan[i].ccap * 2, 2ull * probs[i].d * plan[i].c);
+                again.push_back(i);
+                continue;
+            }
+            if (o.status == ST_INVAL) return fail(ctx, CSP_EINVAL, "batch problem has a zero edge or A and B overlap");
+            if (o.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "batch problem did not finish");
+            out[i].T = o.res[0];
+            out[i].X = o.res[1];
+            out[i].x = o.res[2];
+            out[i].Y = o.res[3];
+            out[i].F2 = o.res[4];
+            if (cnt) {
+                cnt[i].C = (int64_t)o.ctr[0];
+                cnt[i].U = (int64_t)o.ctr[1];
+                cnt[i].D = (int64_t)o.ctr[2];
+                cnt[i].E = (int64_t)o.ctr[3];
+                cnt[i].R = (int64_t)o.ctr[4];
+                cnt[i].P = (int64_t)o.ctr[5];
+                cnt[i].I = (int64_t)o.ctr[6];
+            }
+        }
+        todo.swap(again);
+    }
+    ctx->last_ms = total_ms;
     return CSP_OK;
 }
 

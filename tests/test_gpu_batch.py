@@ -1,0 +1,112 @@
+"""Batched solves (one persistent launch per dimension): every problem's T,
+X, x, Y, F2, labels and counters equal the oracle's, and equal the same
+problem solved alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1511_06441_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def solver(torch):
+    from paper_1511_06441_amd import csp
+    s = csp.Solver(0)
+    yield s
+    s.close()
+
+
+def _batch(solver, torch, insts):
+    from paper_1511_06441_amd import csp
+    dev = [csp.to_device(i) for i in insts]
+    labs = [torch.zeros(i.N, dtype=torch.int32, device="cuda") for i in insts]
+    res, cnt = csp.csp_solve_batch(solver.ctx, dev, labels=labs)
+    torch.cuda.synchronize()
+    _say("  batch kernel ms %.3f" % csp.csp_last_kernel_ms(solver.ctx))
+    return res, cnt, [l.cpu().numpy().view(np.uint32) for l in labs]
+
+
+def _check_vs_oracle(inst, res, cnt, lab):
+    from oracle import oracle as O
+    ref = O.solve_instance(inst)
+    assert res.tuple() == ref.tuple(), (inst.name, res.tuple(), ref.tuple())
+    assert cnt.asdict() == ref.counters, (inst.name, cnt.asdict(), ref.counters)
+    assert np.array_equal(lab, ref.labels), inst.name
+
+
+def test_mixed_small_batch_vs_oracle(solver, torch):
+    insts = [gen.mixed_instance(41, j, lo2=(8, 48), lo3=(4, 16)) for j in range(48)]
+    _say("mixed small batch of", len(insts))
+    res, cnt, labs = _batch(solver, torch, insts)
+    for inst, r, c, l in zip(insts, res, cnt, labs):
+        _check_vs_oracle(inst, r, c, l)
+
+
+def test_gangs_vs_oracle(solver, torch):
+    """Problems too large for one workgroup's LDS run on gangs of workgroups."""
+    insts = [gen.opposite_faces(2, 420, 3, 9, 9, 3000),      # 176,400 vertices
+             gen.opposite_faces(3, 52, 4, 12, 12, 600),      # 140,608 vertices
+             gen.opposite_faces(2, 300, 5, 4, 4, 1200),
+             gen.square64(1), gen.square64(2),
+             gen.opposite_faces(3, 20, 6, 7, 7, 160)]
+    for i, inst in enumerate(insts):
+        inst.name = f"gang{i}"
+    _say("gang batch")
+    res, cnt, labs = _batch(solver, torch, insts)
+    for inst, r, c, l in zip(insts, res, cnt, labs):
+        _check_vs_oracle(inst, r, c, l)
+
+
+def test_batch_equals_alone(solver, torch):
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(41, j, lo2=(16, 200), lo3=(8, 40)) for j in range(24)]
+    res, cnt, labs = _batch(solver, torch, insts)
+    for inst, r, c, l in zip(insts, res, cnt, labs):
+        di = csp.to_device(inst)
+        lab = torch.zeros(inst.N, dtype=torch.int32, device="cuda")
+        r1, c1 = solver.solve(di, labels=lab)
+        torch.cuda.synchronize()
+        assert r.tuple() == r1.tuple() and c.asdict() == c1.asdict(), inst.name
+        assert np.array_equal(l, lab.cpu().numpy().view(np.uint32)), inst.name
+
+
+def test_batch_overflow_retry(solver, torch):
+    """A tiny starting wheel forces per-problem retries; results are unchanged."""
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(7, j, lo2=(8, 64), lo3=(4, 20)) for j in range(16)]
+    csp.csp_set_pool_hint(solver.ctx, 1)
+    try:
+        res, cnt, labs = _batch(solver, torch, insts)
+    finally:
+        csp.csp_set_pool_hint(solver.ctx, 0)
+    for inst, r, c, l in zip(insts, res, cnt, labs):
+        _check_vs_oracle(inst, r, c, l)
+
+
+def test_config4_sample_vs_plain(solver, torch):
+    """The first 64 problems of the 1,024-problem mixed batch (master seed 41):
+    batched results equal plain single-problem solves."""
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(41, j) for j in range(64)]
+    _say("config-4 sample, vertices", sum(i.N for i in insts))
+    res, cnt, labs = _batch(solver, torch, insts)
+    for inst, r, c in zip(insts, res, cnt):
+        di = csp.to_device(inst)
+        r1, c1 = solver.solve(di)
+        assert r.tuple() == r1.tuple() and c.asdict() == c1.asdict(), inst.name
+        assert r.T < 0 or 0 < r.F2 < inst.M
