@@ -43,6 +43,79 @@ WORKLOADS = {
                      build=lambda gen: [gen.square64(1)], sample_index=0),
 }
 
+BATCH_DESC = ("1,024 independent problems (master seed 41): d in {2,3}, side log-uniform in [32,512] (d=2) / "
+              "[16,160] (d=3), f1,f2 iid U{1..K} with K in 3..50 per problem, A/B = faces x=0 / x=n-1, "
+              "M = round((1.5..4) n (K+1)/2); 306,237,961 vertices in all")
+
+
+def mixed_on_device(gen, csp, master, count, lo2=(32, 512), lo3=(16, 160)):
+    """Problems of the mixed batch, drawn on the GPU with the seeded generator."""
+    out = []
+    for j in range(count):
+        s, d, n, K, M = gen.mixed_params(master, j, lo2, lo3)
+        f1, f2 = gen.lattice_edges_torch(d, n, s, K, K, device="cuda")
+        A = gen.face_mask_torch(d, n, 0, 0, "cuda")
+        B = gen.face_mask_torch(d, n, 0, n - 1, "cuda")
+        out.append(csp.DeviceInstance(d, n, f1, f2, A, B, M))
+    return out
+
+
+def run_batch(args):
+    import torch
+    from paper_1511_06441_amd import csp
+    from paper_1511_06441_amd import inputs as gen
+
+    count = args.batch_count
+    dev = mixed_on_device(gen, csp, 41, count)
+    torch.cuda.synchronize()
+    solver = csp.Solver(0)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        csp.csp_solve_batch(solver.ctx, dev, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = []
+    res = cnt = None
+    for _ in range(args.steps):
+        res, cnt = csp.csp_solve_batch(solver.ctx, dev, stream=stream)
+        kern.append(csp.csp_last_kernel_ms(solver.ctx))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    R = sum(c.R for c in cnt)
+    bytes_step = sum(algorithmic_bytes(di.N, c.asdict()) for di, c in zip(dev, cnt))
+    kms = sum(kern) / len(kern)
+    achieved = bytes_step / (kms * 1e-3) / 1e9
+    line = {
+        "metric": "active-edge relaxations/s",
+        "value": R * args.steps / wall,
+        "unit": "relaxations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic (seeded splitmix64 lattices, drawn on the GPU)",
+        "config": {"workload": "batch%d" % count, "desc": BATCH_DESC if count == 1024 else "first %d problems" % count,
+                   "solves_per_step": count, "parallelism": "single GPU"},
+        "solves_per_s": count * args.steps / wall,
+        "roofline": {"bound": "hbm", "kernel": "k_batch<2>, k_batch<3>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_ms_avg": kms, "algorithmic_bytes_per_step": bytes_step},
+        "cpu_baseline": None,
+    }
+    if args.plain:
+        # the same problems as sequential single-problem launches
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        same = True
+        for di, r in zip(dev, res):
+            rp, _ = solver.solve(di, stream=stream)
+            same = same and rp.tuple() == r.tuple()
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t1
+        line["plain"] = {"solves_per_s": count / pw, "seconds": pw, "results_equal": same,
+                         "batched_speedup": (count * args.steps / wall) / (count / pw)}
+    print(json.dumps(line), flush=True)
+    solver.close()
+
 
 def algorithmic_bytes(N, c):
     """Bytes the method must move for one solve (label init, own label per
@@ -69,13 +142,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["batch1024"])
+    ap.add_argument("--batch-count", type=int, default=1024)
+    ap.add_argument("--plain", action="store_true", help="batch workload: also time sequential plain launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the path does not shard "
               "across GPUs in this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch1024":
+        run_batch(args)
+        return
 
     import torch
     from paper_1511_06441_amd import csp

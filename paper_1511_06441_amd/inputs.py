@@ -278,3 +278,62 @@ def poisson_arrivals(count: int, qps: float, seed: int = 52) -> np.ndarray:
     u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
     gaps = -np.log1p(-u) / qps
     return np.cumsum(gaps)
+
+
+# ----------------------------------------------------------------------------
+# the same draws, generated on a torch device (for large workloads)
+# ----------------------------------------------------------------------------
+
+def _i64(v: int) -> int:
+    """Two's-complement int64 value of a 64-bit pattern."""
+    v &= MASK64
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _shr(z, k):
+    """Logical right shift of int64 tensors holding 64-bit patterns."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _mix64_t(z):
+    z = (z ^ _shr(z, 30)) * _i64(_C1)
+    z = (z ^ _shr(z, 27)) * _i64(_C2)
+    return z ^ _shr(z, 31)
+
+
+def lattice_edges_torch(d: int, n: int, seed: int, K1: int, K2: int, device="cuda",
+                        f1_const=None, f2_const=None, chunk: int = 1 << 24):
+    """Same arrays as ``lattice_edges`` (bit for bit), built with torch on ``device``."""
+    import torch
+    N = n ** d
+    total = d * N
+    out = []
+    for which, K, const in ((1, K1, f1_const), (2, K2, f2_const)):
+        f = torch.empty(total, dtype=torch.uint8, device=device)
+        if const is not None:
+            f.fill_(const)
+        else:
+            sigma = _i64(edge_stream_state(seed, which))
+            for s0 in range(0, total, chunk):
+                c = min(chunk, total - s0)
+                i = torch.arange(s0 + 1, s0 + c + 1, dtype=torch.int64, device=device)
+                z = _mix64_t(sigma + i * _i64(GAMMA))
+                f[s0:s0 + c] = (1 + ((_shr(z, 32) * K) >> 32)).to(torch.uint8)
+        out.append(f)
+    # zero the padding entries: (k, u) with c_k(u) == n-1
+    for f in out:
+        for k in range(d):
+            g = f[k * N:(k + 1) * N].view(*([n] * d))
+            idx = [slice(None)] * d
+            idx[d - 1 - k] = n - 1
+            g[tuple(idx)] = 0
+    return out[0], out[1]
+
+
+def face_mask_torch(d: int, n: int, axis: int, coord: int, device="cuda"):
+    import torch
+    m = torch.zeros((n,) * d, dtype=torch.uint8, device=device)
+    idx = [slice(None)] * d
+    idx[d - 1 - axis] = coord
+    m[tuple(idx)] = 1
+    return m.reshape(-1)

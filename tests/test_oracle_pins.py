@@ -345,3 +345,13 @@ def test_worked_example_vs_state_dijkstra():
     r = O.solve_graph(graph, A, B, ex["M"])
     _check_tuple(r, T, X, x, Y, F2)
     assert np.array_equal(r.labels.astype(np.int64), lab)
+
+
+def test_torch_generator_matches_numpy():
+    """The on-device generator draws exactly the numpy generator's values."""
+    for d, n, seed, K1, K2 in ((2, 37, 5, 7, 9), (3, 11, 41, 50, 3), (1, 100, 2, 255, 1)):
+        a1, a2 = gen.lattice_edges(d, n, seed, K1, K2)
+        b1, b2 = gen.lattice_edges_torch(d, n, seed, K1, K2, device="cpu", chunk=97)
+        assert np.array_equal(a1, b1.numpy()) and np.array_equal(a2, b2.numpy())
+        for ax in range(d):
+            assert np.array_equal(gen.face_mask(d, n, ax, 0), gen.face_mask_torch(d, n, ax, 0, "cpu").numpy())
