@@ -208,7 +208,8 @@ def main():
         "results": [dict(T=r.T, X=r.X, x=r.x, Y=r.Y, F2=r.F2, **c.asdict()) for r, c, _ in runs[0]],
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_solve<{insts[0].d}>",
+            "kernel": (f"k_ranges<{insts[0].d}>" if csp.csp_last_path(solver.ctx) == 1
+                       else f"k_solve<{insts[0].d}>"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
