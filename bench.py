@@ -117,6 +117,78 @@ def run_batch(args):
     solver.close()
 
 
+SERVE_DESC = ("Poisson arrivals (seed 52) of requests from master seed 51: d in {2,3}, sides log-uniform "
+              "64..1024 (2-D) / 32..256 (3-D), f1,f2 iid U{1..K}, K in 3..50, faces x=0 -> x=n-1, "
+              "M = round((1.5..4) n (K+1)/2); each request is a solve plus the full path reconstruction "
+              "by repeated solves")
+
+
+def run_serve(args):
+    import numpy as np
+    import torch
+    from paper_1511_06441_amd import csp, serving
+    from paper_1511_06441_amd import inputs as gen
+
+    count = args.serve_count
+    params = gen.serving_params(count, 51)
+    dev = []
+    for (s, d, n, K, M) in params:
+        f1, f2 = gen.lattice_edges_torch(d, n, s, K, K, device="cuda")
+        dev.append(csp.DeviceInstance(d, n, f1, f2, gen.face_mask_torch(d, n, 0, 0, "cuda"),
+                                      gen.face_mask_torch(d, n, 0, n - 1, "cuda"), M))
+    torch.cuda.synchronize()
+    print(f"# serve: {count} requests, {sum(x.N for x in dev)} vertices in all", file=sys.stderr, flush=True)
+    solver = csp.Solver(0)
+    server = csp.Server(solver, arena_bytes=args.serve_arena_gb << 30, max_jobs=256)
+    # warm-up: the smallest request
+    small = min(range(count), key=lambda k: dev[k].N)
+    serving.replay(server, [dev[small]])
+    sat = serving.replay(server, dev)
+    sat_rps = count / sat.makespan
+    solves = sum(c.solves for c in sat.completions.values())
+    R = sum(c.counters["R"] + c.chain_counters["R"] for c in sat.completions.values())
+    print(f"# saturation: {sat_rps:.3f} requests/s over {sat.makespan:.2f} s", file=sys.stderr, flush=True)
+    sweep = []
+    for frac in args.serve_fracs:
+        arr = gen.poisson_arrivals(count, frac * sat_rps, 52)
+        tr = serving.replay(server, dev, arr)
+        same = all(tr.completions[k].res == sat.completions[k].res and
+                   tr.completions[k].path == sat.completions[k].path for k in range(count))
+        sweep.append({"qps": frac * sat_rps, "fraction_of_saturation": frac,
+                      "p50_s": tr.percentile(50), "p99_s": tr.percentile(99),
+                      "mean_s": float(tr.latency.mean()), "makespan_s": tr.makespan,
+                      "requests_per_s": count / tr.makespan, "results_equal_saturated": same})
+        print(f"# qps {frac:.2f}x: p50 {tr.percentile(50):.3f} s p99 {tr.percentile(99):.3f} s",
+              file=sys.stderr, flush=True)
+    line = {
+        "metric": "active-edge relaxations/s", "value": R / sat.makespan, "unit": "relaxations/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": sat.makespan * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic (seeded splitmix64 lattices, drawn on the GPU)",
+        "config": {"workload": f"serve{count}", "desc": SERVE_DESC, "requests": count,
+                   "parallelism": "single GPU"},
+        "saturation": {"requests_per_s": sat_rps, "solves_per_s": solves / sat.makespan,
+                       "p50_s": sat.percentile(50), "p99_s": sat.percentile(99), "solves": solves},
+        "sweep": sweep, "roofline": None, "cpu_baseline": None,
+    }
+    if args.plain:
+        # the same requests one after another with plain launches
+        t0 = time.perf_counter()
+        same = True
+        for k, di in enumerate(dev):
+            scratch = torch.zeros(di.N, dtype=torch.uint8, device="cuda")
+            path, res = solver.reconstruct(di, scratch)
+            c = sat.completions[k]
+            same = same and res.tuple() == c.res and path.tolist() == c.path
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        line["plain"] = {"requests_per_s": count / pw, "seconds": pw, "results_equal": same,
+                         "served_speedup": sat_rps / (count / pw)}
+    server.close()
+    solver.close()
+    print(json.dumps(line), flush=True)
+
+
 def algorithmic_bytes(N, c):
     """Bytes the method must move for one solve (label init, own label per
     improvement, f1+f2+neighbour label per test, one flow record written per
@@ -142,9 +214,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["batch1024"])
+    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["batch1024", "serve"])
     ap.add_argument("--batch-count", type=int, default=1024)
     ap.add_argument("--plain", action="store_true", help="batch workload: also time sequential plain launches")
+    ap.add_argument("--serve-count", type=int, default=32)
+    ap.add_argument("--serve-arena-gb", type=int, default=64)
+    ap.add_argument("--serve-fracs", type=float, nargs="*", default=[0.25, 0.5, 0.8])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -154,6 +229,9 @@ def main():
 
     if args.workload == "batch1024":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     import torch

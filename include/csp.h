@@ -166,6 +166,75 @@ int csp_last_path(const csp_ctx *ctx);
 int csp_set_phase_timing(csp_ctx *ctx, int on);
 int csp_last_phase_us(const csp_ctx *ctx, double *us);
 
+/* ---- Serving: continuous batching of solves and reconstructions --------
+ *
+ * A server runs one persistent kernel whose workers (one workgroup per CU)
+ * keep taking work while it runs: requests submitted while others are on
+ * the GPU are admitted as soon as job slots, workers and arena memory free
+ * up, in submission order, and run beside them.  A request is one solve
+ * (sections 4-6) and, when asked, the path reconstruction of section 2
+ * (repeated solves with B' = {Y}, M' = F2 - f2(x) + 1 until Y is in A),
+ * carried out by the same workers on device-resident state.  Results are
+ * identical to csp_solve_dev / csp_reconstruct_dev on the request alone.
+ *
+ * The server owns an HBM arena of `arena_bytes` for per-request state
+ * (packed edges, frontier lists, timing wheel, candidate buffers); a
+ * request's footprint is about 20 bytes per vertex plus 8 bytes per wheel
+ * flow (6 d N flows to start, doubled on overflow).  Admission waits until
+ * the footprint fits.  The caller keeps a request's f1, f2, A, B (device
+ * memory) valid and unchanged until its completion is returned, and makes
+ * sure they are complete on the device before submitting (the workers read
+ * them from their own stream).
+ *
+ * Progress is made inside csp_serve_submit and csp_serve_poll; call poll
+ * regularly.  When the server has nothing to do the workers leave, so the
+ * GPU is free for other kernels; the next admitted request starts them
+ * again.  One host thread uses a server at a time. */
+typedef struct csp_server csp_server;
+
+typedef struct {
+    int d;
+    int64_t n;
+    const uint8_t *f1, *f2, *A, *B;   /* device pointers, as for csp_solve_dev */
+    uint32_t M;
+    int reconstruct;                  /* nonzero: also the path A -> X */
+    uint64_t tag;                     /* returned unchanged in the completion */
+} csp_request;
+
+typedef struct {
+    uint64_t tag;
+    int status;                       /* CSP_OK or this request's error */
+    csp_result res;                   /* as from csp_solve_dev */
+    csp_counters cnt;                 /* the first solve */
+    csp_counters cnt_chain;           /* the reconstruction re-solves: U, D, E, R
+                                         summed; C, P, I of the last one */
+    int64_t solves;                   /* 1 + re-solves */
+    int64_t path_len;                 /* vertices of the path A -> X (0 if none
+                                         or not asked for) */
+    const int64_t *path;              /* owned by the server; valid until the
+                                         next csp_serve_poll or csp_serve_close */
+} csp_completion;
+
+/* Create a server on ctx's device with an arena of arena_bytes (>= 1 MiB)
+ * and at most max_jobs (1..4096) requests on the GPU at once. */
+int csp_serve_open(csp_ctx *ctx, uint64_t arena_bytes, int max_jobs, csp_server **out);
+
+/* Queue a request.  CSP_EINVAL for bad shapes or null pointers, CSP_ENOMEM
+ * when it could never fit the arena.  Errors found on the device (a zero
+ * edge, A and B not disjoint) come back in the completion's status. */
+int csp_serve_submit(csp_server *s, const csp_request *req);
+
+/* Collect up to cap completions (in completion order) into out; *count
+ * gets how many.  Never blocks. */
+int csp_serve_poll(csp_server *s, csp_completion *out, int cap, int *count);
+
+/* Requests waiting for admission or collection, and requests on the GPU. */
+int csp_serve_pending(const csp_server *s, int *queued, int *running);
+
+/* Finish the requests on the GPU, stop the workers and free the server.
+ * Requests not yet admitted are dropped. */
+int csp_serve_close(csp_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ EXPORTED = (
     "csp_create", "csp_destroy", "csp_last_error", "csp_solve_dev", "csp_solve",
     "csp_reconstruct_dev", "csp_last_kernel_ms", "csp_set_pool_hint",
     "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us", "csp_set_path",
-    "csp_last_path", "csp_solve_batch",
+    "csp_last_path", "csp_solve_batch", "csp_serve_open", "csp_serve_submit",
+    "csp_serve_poll", "csp_serve_pending", "csp_serve_close",
 )
 
 
@@ -49,6 +50,18 @@ class csp_counters(ctypes.Structure):
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class csp_request(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int64), ("f1", ctypes.c_void_p),
+                ("f2", ctypes.c_void_p), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("M", ctypes.c_uint32), ("reconstruct", ctypes.c_int), ("tag", ctypes.c_uint64)]
+
+
+class csp_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("res", csp_result),
+                ("cnt", csp_counters), ("cnt_chain", csp_counters), ("solves", ctypes.c_int64),
+                ("path_len", ctypes.c_int64), ("path", ctypes.POINTER(ctypes.c_int64))]
 
 
 def _load():
@@ -87,6 +100,16 @@ def _load():
     lib.csp_set_phase_timing.restype = i32
     lib.csp_last_phase_us.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
     lib.csp_last_phase_us.restype = i32
+    lib.csp_serve_open.argtypes = [p, ctypes.c_uint64, i32, ctypes.POINTER(p)]
+    lib.csp_serve_open.restype = i32
+    lib.csp_serve_submit.argtypes = [p, ctypes.POINTER(csp_request)]
+    lib.csp_serve_submit.restype = i32
+    lib.csp_serve_poll.argtypes = [p, ctypes.POINTER(csp_completion), i32, ctypes.POINTER(i32)]
+    lib.csp_serve_poll.restype = i32
+    lib.csp_serve_pending.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.csp_serve_pending.restype = i32
+    lib.csp_serve_close.argtypes = [p]
+    lib.csp_serve_close.restype = i32
     return lib
 
 
@@ -270,3 +293,88 @@ class Solver:
         cap = cap if cap is not None else di.N + 1
         return csp_reconstruct_dev(self.ctx, di.d, di.n, di.f1, di.f2, di.A, di.B, di.M,
                                    scratch_mask, cap, stream=stream)
+
+
+# --- serving -----------------------------------------------------------------
+
+def csp_serve_open(ctx, arena_bytes: int, max_jobs: int):
+    srv = ctypes.c_void_p()
+    _check(ctx, lib.csp_serve_open(ctx, arena_bytes, max_jobs, ctypes.byref(srv)))
+    return srv
+
+
+def csp_serve_submit(ctx, srv, di: DeviceInstance, reconstruct=True, tag=0, M=None):
+    q = csp_request(di.d, di.n, di.f1.data_ptr(), di.f2.data_ptr(), di.A.data_ptr(), di.B.data_ptr(),
+                    di.M if M is None else M, 1 if reconstruct else 0, tag)
+    _check(ctx, lib.csp_serve_submit(srv, ctypes.byref(q)))
+
+
+@dataclass
+class Completion:
+    tag: int
+    status: int
+    res: tuple
+    counters: dict
+    chain_counters: dict
+    solves: int
+    path: list
+
+
+def csp_serve_poll(ctx, srv, cap=64):
+    buf = (csp_completion * cap)()
+    n = ctypes.c_int()
+    _check(ctx, lib.csp_serve_poll(srv, buf, cap, ctypes.byref(n)))
+    out = []
+    for k in range(n.value):
+        c = buf[k]
+        path = [c.path[i] for i in range(c.path_len)] if c.path_len > 0 else []
+        out.append(Completion(c.tag, c.status, c.res.tuple(), c.cnt.asdict(), c.cnt_chain.asdict(),
+                              c.solves, path))
+    return out
+
+
+def csp_serve_pending(srv):
+    q, r = ctypes.c_int(), ctypes.c_int()
+    _check(None, lib.csp_serve_pending(srv, ctypes.byref(q), ctypes.byref(r)))
+    return q.value, r.value
+
+
+def csp_serve_close(srv):
+    _check(None, lib.csp_serve_close(srv))
+
+
+class Server:
+    """Continuous-batching server on one libcsp context: submit requests while
+    others run, poll for completions."""
+
+    def __init__(self, solver: Solver, arena_bytes: int = 8 << 30, max_jobs: int = 256):
+        self.solver = solver
+        self.srv = csp_serve_open(solver.ctx, arena_bytes, max_jobs)
+
+    def submit(self, di: DeviceInstance, reconstruct=True, tag=0):
+        csp_serve_submit(self.solver.ctx, self.srv, di, reconstruct=reconstruct, tag=tag)
+
+    def poll(self, cap=64):
+        return csp_serve_poll(self.solver.ctx, self.srv, cap)
+
+    def pending(self):
+        return csp_serve_pending(self.srv)
+
+    def drain(self, timeout_s=120.0):
+        """Poll until nothing is queued or running; returns the completions."""
+        import time
+        out = []
+        t0 = time.perf_counter()
+        while True:
+            out.extend(self.poll())
+            q, r = self.pending()
+            if q == 0 and r == 0:
+                return out
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"serving did not drain in {timeout_s} s ({q} queued, {r} running)")
+            time.sleep(0.0002)
+
+    def close(self):
+        if self.srv:
+            csp_serve_close(self.srv)
+            self.srv = None

@@ -57,6 +57,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <vector>
 
 #include "csp.h"
@@ -910,12 +912,19 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
     return ok;
 }
 
+// Offset of the neighbour in direction dir (0..D-1: -stride[D-1..0],
+// D..2D-1: +stride[0..D-1]).
+template <int D> __device__ __forceinline__ long long dir_offset(long long n, int dir)
+{
+    const int k = dir < D ? D - 1 - dir : dir - D;
+    long long st = 1;
+    for (int j = 0; j < k; ++j) st *= n;
+    return dir < D ? -st : st;
+}
+
 // One range-owned solve (a "job"): everything a gang of g workgroups needs.
 struct RJ {
     long long n, N;
-    long long off[8];              // neighbour offset per direction
-    long long offq[8];             // floor(off / c)
-    long long offr[8];             // off - c * floor(off / c), in [0, c)
     long long c;                   // vertices per range
     int d;
     int K;                         // neighbours lie within K ranges
@@ -996,8 +1005,21 @@ constexpr unsigned SF_BAD = 1u << 28;      // an edge with f1 or f2 equal to 0
 //   barrier: next event time, flags, counts, best B key (Steps 1, 6)
 //   accept candidates shipped at t_prev against this range's labels
 //   arrival (Steps 1-3, 8): deliver bucket t, commit labels, build I_t
+// What every member of the gang knows when a solve ends; yd (direction of
+// the last edge seen from X) is known only to X's owner.
+struct RunRes {
+    int status;
+    int found;
+    long long t;
+    unsigned X, LX, yd;
+};
+
+// M and B of the solve are arguments so that a chain of solves on one
+// lattice (reconstruction) can change them: B is the mask p.B, or the single
+// vertex bvert when bvert >= 0.  epoch continues over the gang's barriers.
 template <int D>
-__device__ void range_run(const RJ &p, unsigned r, unsigned *smem)
+__device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M, long long bvert, unsigned &epoch,
+                            Out *out)
 {
     using RT = typename Rec<D>::T;
     __shared__ unsigned s_wave[NWAVES];
@@ -1014,20 +1036,21 @@ __device__ void range_run(const RJ &p, unsigned r, unsigned *smem)
     const unsigned tid = threadIdx.x, lane = lane_id();
     const unsigned G = p.g;
     const bool lead = r == 0;
+    const long long n = p.n, N = p.N, c = p.c;
+    // neighbour offsets split into whole ranges (floor) and a remainder in [0, c)
     long long offq[2 * D], offr[2 * D], offv[2 * D];
 #pragma unroll
     for (int dir = 0; dir < 2 * D; ++dir) {
-        offq[dir] = p.offq[dir];
-        offr[dir] = p.offr[dir];
-        offv[dir] = p.off[dir];
+        const long long o = dir_offset<D>(n, dir);
+        const long long q = o >= 0 ? o / c : -((-o + c - 1) / c);
+        offv[dir] = o;
+        offq[dir] = q;
+        offr[dir] = o - q * c;
     }
-    const long long n = p.n, N = p.N, c = p.c;
     const long long base = (long long)r * c;
     const unsigned cr = (unsigned)max(0ll, min(c, N - base));
     const int K = p.K, NO = 2 * K + 1;
     RT *rec = static_cast<RT *>(p.rec);
-    Out *out = p.out;
-    unsigned epoch = 0;
 
     const unsigned cw = (unsigned)((c + 31) / 32);
     const bool l16 = p.lt == 2;
@@ -1118,10 +1141,10 @@ __device__ void range_run(const RJ &p, unsigned r, unsigned *smem)
                                 pr[6] | (pr[7] << 16));
             }
             rec[v] = rv;
-            const bool a = p.A[v] != 0, b = p.B[v] != 0;
+            const bool a = p.A[v] != 0, b = bvert >= 0 ? v == bvert : p.B[v] != 0;
             if (a && b) bad |= 2;
             if (a) {
-                lset(lab, l16, i, p.M);
+                lset(lab, l16, i, M);
                 atomicOr(&fb[i >> 5], 1u << (i & 31));
             }
             if (b) atomicOr(&bb[i >> 5], 1u << (i & 31));
@@ -1201,6 +1224,8 @@ __device__ void range_run(const RJ &p, unsigned r, unsigned *smem)
     const unsigned CS = p.cand_cap;
     uint2 *wheel = p.pool + (unsigned long long)r * W * S;
 
+    RunRes rr;
+    rr.X = rr.LX = 0;
     long long t = 0, t_prev = 0;
     unsigned cyc = 0, par = 0;
     unsigned F = 0;                     // flows delivered this cycle
@@ -1327,10 +1352,12 @@ __device__ void range_run(const RJ &p, unsigned r, unsigned *smem)
                         out->res[1] = X;
                         out->res[2] = (long long)k * N + (lower ? Y : (long long)X);
                         out->res[3] = Y;
-                        out->res[4] = (long long)p.M - (long long)LX;
+                        out->res[4] = (long long)M - (long long)LX;
                     }
                 }
             }
+            rr.X = X;
+            rr.LX = LX;
             status = ST_DONE;
             break;
         }
@@ -1449,6 +1476,12 @@ __device__ void range_run(const RJ &p, unsigned r, unsigned *smem)
         }
     }
     __syncthreads();
+    rr.status = status;
+    rr.found = found ? 1 : 0;
+    rr.t = t;
+    rr.yd = s_ydir;
+    __syncthreads();
+    return rr;
 }
 
 // Single solve: the whole grid is one gang; range r of physical block b is
@@ -1459,7 +1492,8 @@ __global__ void __launch_bounds__(BLOCK) k_ranges(RJ p)
     extern __shared__ unsigned smem[];
     const unsigned G = gridDim.x;
     const unsigned r = (G % NGRP) == 0 ? (blockIdx.x % NGRP) * (G / NGRP) + blockIdx.x / NGRP : blockIdx.x;
-    range_run<D>(p, r, smem);
+    unsigned epoch = 0;
+    (void)range_run<D>(p, r, smem, p.M, -1, epoch, p.out);
 }
 
 // Batched solves in one persistent launch.  Work is a list of (job, range)
@@ -1489,8 +1523,292 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a)
         if (sl >= a.nslots) break;
         const unsigned jb = __builtin_amdgcn_readfirstlane(a.slot_job[sl]);
         const unsigned r = __builtin_amdgcn_readfirstlane(a.slot_range[sl]);
-        range_run<D>(a.jobs[jb], r, smem);
+        const RJ &job = a.jobs[jb];
+        unsigned epoch = 0;
+        (void)range_run<D>(job, r, smem, job.M, -1, epoch, job.out);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Serving: one persistent launch that keeps taking solves while it runs.
+//
+// The host publishes jobs in host-coherent (fine-grained) memory: a job
+// table, a ring of (job, range) slots and a tail counter.  Workers (one
+// workgroup per CU) claim slots in order by compare-and-swap on a device
+// word that holds the number of claimed slots, so a slot is taken only once
+// it is published, and the host publishes all slots of a job at once.  One
+// idle worker at a time (the watcher) reads the host's tail and mirrors it
+// into device memory, so idle workers spin on L2 rather than on the bus.
+// A job is the solve of its range, then, when asked, the reconstruction
+// chain of section 2 (re-solve with B' = {Y} and M' = F2 - f2(x) + 1 until
+// Y is in A), run by the same gang with the lattice still resident.  The
+// last member to finish writes the completion record to host memory.
+// Workers leave when the host raises stop, or when the host has not beaten
+// its heartbeat for `stale` ticks, and only when every published slot has
+// been claimed, so no gang is ever left short of members.
+// ---------------------------------------------------------------------------
+
+// Completion record of a served job (host-coherent memory).
+struct Done {
+    long long res[5];                  // T X x Y F2 of the first solve
+    unsigned long long ctr[8];         // counters of the first solve
+    unsigned long long ctr_chain[8];   // reconstruction solves (U D E R summed)
+    long long path_len;
+    long long solves;
+    int status;
+    int pad;
+    unsigned long long seq;            // written last; the host waits for it
+};
+
+struct SJ {
+    RJ rj;
+    Out *out0;                         // first solve
+    Out *outc;                         // reconstruction solves
+    unsigned *done_cnt;                // members finished (zero between jobs)
+    long long *path;                   // host-coherent; X, Y, Y', ... until A
+    long long path_cap;
+    Done *done;                        // host-coherent
+    unsigned long long seq;
+    int recon;
+    int pad;
+};
+
+// Host-coherent control block.
+struct SrvCtl {
+    unsigned long long tail;           // slots published
+    unsigned long long heartbeat;
+    unsigned stop;
+    unsigned pad[27];
+};
+
+constexpr unsigned long long SRV_QUIT = 1ull << 63;
+
+struct ServeArgs {
+    const SJ *jobs;                    // host-coherent [max jobs]
+    const unsigned *slots;             // host-coherent [ring][2] (job, range)
+    unsigned ring;                     // power of two
+    const SrvCtl *ctl;
+    unsigned long long *state;         // device: claimed slots | SRV_QUIT
+    unsigned long long *dtail;         // device mirror of ctl->tail
+    unsigned *watch;                   // device: 1 while a watcher polls the host
+    unsigned long long stale;          // wall-clock ticks
+    unsigned max_jobs;
+};
+
+__device__ __forceinline__ unsigned long long ld_sys64(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ unsigned ld_sys32(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void st_sys64(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void st_sys64(long long *p, long long v)
+{
+    st_sys64(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
+__device__ __forceinline__ bool cas64(unsigned long long *p, unsigned long long expect, unsigned long long want)
+{
+    return __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Next slot for the calling worker (thread 0), or ~0 when the worker leaves.
+__device__ unsigned long long serve_claim(const ServeArgs &a)
+{
+    bool watcher = false;
+    unsigned long long hb_last = 0, t_seen = wall_clock64();
+    for (;;) {
+        const unsigned long long st = __hip_atomic_load(a.state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (st & SRV_QUIT) {
+            if (watcher) __hip_atomic_store(a.watch, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return ~0ull;
+        }
+        unsigned long long tl = __hip_atomic_load(a.dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!watcher && st >= tl) {
+            unsigned z = 0;
+            watcher = __hip_atomic_compare_exchange_strong(a.watch, &z, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            if (watcher) {
+                hb_last = ld_sys64(&a.ctl->heartbeat);
+                t_seen = wall_clock64();
+            }
+        }
+        if (watcher) {
+            tl = ld_sys64(&a.ctl->tail);
+            if (tl > __hip_atomic_load(a.dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                __hip_atomic_store(a.dtail, tl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (st < tl) {
+            if (cas64(a.state, st, st + 1)) {
+                if (watcher) __hip_atomic_store(a.watch, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                return st;
+            }
+            continue;
+        }
+        if (watcher) {
+            const unsigned long long hb = ld_sys64(&a.ctl->heartbeat), now = wall_clock64();
+            if (hb != hb_last) {
+                hb_last = hb;
+                t_seen = now;
+            }
+            if (ld_sys32(&a.ctl->stop) || now - t_seen > a.stale) {
+                (void)cas64(a.state, st, st | SRV_QUIT);   // fails if a slot was claimed meanwhile
+                continue;
+            }
+            __builtin_amdgcn_s_sleep(32);
+        } else {
+            __builtin_amdgcn_s_sleep(127);
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void serve_job(const SJ &sj, unsigned r, unsigned *smem)
+{
+    const RJ &p = sj.rj;
+    const unsigned tid = threadIdx.x, G = p.g;
+    if (r == 0 && tid == 0) {
+        // before the gang's first barrier, which publishes it
+        Out *o[2] = {sj.out0, sj.outc};
+        for (int k = 0; k < 2; ++k) {
+            for (int i = 0; i < 5; ++i) o[k]->res[i] = 0;
+            for (int i = 0; i < 8; ++i) o[k]->ctr[i] = 0;
+            o[k]->status = 0;
+        }
+    }
+    unsigned epoch = 0;
+    int status = ST_DONE;
+    long long plen = 0, solves = 0;
+    long long X = -1, T = 0, F2 = 0, bvert = -1;
+    unsigned Mc = p.M, f1x = 0, f2x = 0;
+    for (;;) {
+        const RunRes rr = range_run<D>(p, r, smem, Mc, bvert, epoch, solves ? sj.outc : sj.out0);
+        if (rr.status != ST_DONE) { status = rr.status; break; }
+        if (solves == 0) {
+            if (!rr.found || !sj.recon) break;
+            if (r == 0 && tid == 0) st_sys64(&sj.path[0], (long long)rr.X);
+            plen = 1;
+        } else if (!rr.found || (long long)rr.X != bvert || rr.t != T - (long long)f1x ||
+                   (long long)Mc - (long long)rr.LX != F2 - (long long)f2x) {
+            status = ST_BROKEN;         // a re-solve must end at Y, f1(x) and f2(x) earlier
+            break;
+        }
+        ++solves;
+        X = rr.X;
+        T = rr.t;
+        F2 = (long long)Mc - (long long)rr.LX;
+        // the direction of x is known to X's owner only
+        Comb mine, all;
+        mine.mn = rr.yd;
+        mine.orf = 0;
+        mine.s0 = mine.s1 = mine.s2 = mine.mx = 0;
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all)) { status = ST_BROKEN; break; }
+        const unsigned yd = all.mn;
+        if (yd >= 2u * D || plen >= sj.path_cap) { status = ST_BROKEN; break; }
+        long long oy = 0;
+#pragma unroll
+        for (int dd = 0; dd < 2 * D; ++dd)
+            if ((unsigned)dd == yd) oy = dir_offset<D>(p.n, dd);
+        const long long Y = X + oy;
+        const bool lower = (int)yd < D;
+        const int k = lower ? D - 1 - (int)yd : (int)yd - D;
+        const long long x = (long long)k * p.N + (lower ? Y : X);
+        if (r == 0 && tid == 0) st_sys64(&sj.path[plen], Y);
+        ++plen;
+        if (p.A[Y]) break;
+        f1x = p.f1[x];
+        f2x = p.f2[x];
+        Mc = (unsigned)(F2 - (long long)f2x + 1);
+        bvert = Y;
+    }
+    if (solves == 0) solves = 1;
+    // Leave the barrier lines zero for the next job, then count out; the last
+    // member publishes the completion.
+    __syncthreads();
+    if (tid == 0) {
+        if (G > 1) {
+            unsigned long long *sl = bar_slot(p.bar, r), *fl = bar_flag(p.bar, G, r);
+            for (int k = 0; k < 16; ++k) {
+                st64(&sl[k], 0);
+                st64(&fl[k], 0);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        const unsigned a = __hip_atomic_fetch_add(sj.done_cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == G - 1) {
+            __hip_atomic_store(sj.done_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int br = __hip_atomic_load(&p.bar->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            Done *dn = sj.done;
+            for (int i = 0; i < 5; ++i) st_sys64(&dn->res[i], ld64(reinterpret_cast<const unsigned long long *>(&sj.out0->res[i])));
+            for (int i = 0; i < 8; ++i) {
+                st_sys64(&dn->ctr[i], ld64(&sj.out0->ctr[i]));
+                st_sys64(&dn->ctr_chain[i], ld64(&sj.outc->ctr[i]));
+            }
+            st_sys64(&dn->path_len, plen);
+            st_sys64(&dn->solves, solves);
+            __hip_atomic_store(&dn->status, br ? (int)ST_BROKEN : status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            st_sys64(&dn->seq, sj.seq);
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(BLOCK) k_serve(ServeArgs a)
+{
+    extern __shared__ unsigned smem[];
+    __shared__ SJ s_job;
+    __shared__ unsigned long long s_slot;
+    __shared__ unsigned s_jr[2];
+    constexpr unsigned JW = sizeof(SJ) / 8;
+    static_assert(sizeof(SJ) % 8 == 0, "job words");
+    for (;;) {
+        if (threadIdx.x == 0) s_slot = serve_claim(a);
+        __syncthreads();
+        const unsigned long long sl = s_slot;
+        if (sl == ~0ull) break;
+        if (threadIdx.x < 2) s_jr[threadIdx.x] = ld_sys32(&a.slots[2 * (sl & (a.ring - 1)) + threadIdx.x]);
+        __syncthreads();
+        const unsigned j = __builtin_amdgcn_readfirstlane(s_jr[0]), r = __builtin_amdgcn_readfirstlane(s_jr[1]);
+        if (j >= a.max_jobs) continue;      // not a slot the host wrote
+        const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.jobs + j);
+        unsigned long long *dst = reinterpret_cast<unsigned long long *>(&s_job);
+        for (unsigned i = threadIdx.x; i < JW; i += BLOCK) dst[i] = ld_sys64(src + i);
+        __syncthreads();
+        // the job's fields as wave-uniform values
+        SJ pj;
+        const unsigned *sw = reinterpret_cast<const unsigned *>(&s_job);
+        unsigned *pw = reinterpret_cast<unsigned *>(&pj);
+#pragma unroll
+        for (unsigned i = 0; i < sizeof(SJ) / 4; ++i) pw[i] = __builtin_amdgcn_readfirstlane(sw[i]);
+        __syncthreads();
+        if (r >= pj.rj.g) continue;         // not a slot the host wrote
+        switch (pj.rj.d) {
+        case 1: serve_job<1>(pj, r, smem); break;
+        case 2: serve_job<2>(pj, r, smem); break;
+        case 3: serve_job<3>(pj, r, smem); break;
+        default: serve_job<4>(pj, r, smem); break;
+        }
+        __syncthreads();
+    }
+}
+
+// Clear the quit bit and the watcher flag before a serving launch.
+__global__ void k_serve_reset(unsigned long long *state, unsigned *watch)
+{
+    *state &= ~SRV_QUIT;
+    *watch = 0;
 }
 
 __global__ void k_set_byte(uint8_t *p, long long i, uint8_t v) { p[i] = v; }
@@ -1690,8 +2008,7 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
     return pl;
 }
 
-void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const long long off[8],
-              const uint8_t *f1, const uint8_t *f2, const uint8_t *A, const uint8_t *B, uint32_t M)
+void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const uint8_t *f1, const uint8_t *f2, const uint8_t *A, const uint8_t *B, uint32_t M)
 {
     memset(&p, 0, sizeof(p));
     p.n = n;
@@ -1701,17 +2018,53 @@ void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const
     p.K = plan.K;
     p.lt = plan.lt;
     p.g = (unsigned)plan.G;
-    for (int dir = 0; dir < 8; ++dir) {
-        p.off[dir] = off[dir];
-        const long long q = off[dir] >= 0 ? off[dir] / plan.c : -((-off[dir] + plan.c - 1) / plan.c);
-        p.offq[dir] = q;
-        p.offr[dir] = off[dir] - q * plan.c;
-    }
     p.f1 = f1;
     p.f2 = f2;
     p.A = A;
     p.B = B;
     p.M = M;
+}
+
+// Gang layout of one problem run by persistent workers with `budget` bytes
+// of dynamic LDS each: 16-bit LDS labels when M allows (larger ranges, fewer
+// workgroups), g ranges of c vertices, neighbours within K ranges, a wheel of
+// `pool` flows and candidate buffers of `ccap` entries per (sender, offset).
+struct GangPlan {
+    long long N = 0, c = 0;
+    int g = 1, K = 0, lt = 4;
+    size_t lds = 0;
+    unsigned long long pool = 0, ccap = 1;
+};
+
+int plan_gang(csp_ctx *ctx, size_t budget, int gmax, int d, long long n, long long N, uint32_t M, GangPlan &pl)
+{
+    pl.N = N;
+    pl.lt = M <= 0xFFFFu ? 2 : 4;
+    long long cmax = 0;
+    {
+        long long lo = 1, hi = 1ll << 22;
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) / 2;
+            if (lds_bytes_for(mid, 0, pl.lt) <= budget) lo = mid;
+            else hi = mid - 1;
+        }
+        cmax = lo;
+    }
+    pl.g = (int)std::min<long long>((N + cmax - 1) / cmax, std::min(gmax, GMAX));
+    pl.c = (N + pl.g - 1) / pl.g;
+    if (pl.c > cmax) return fail(ctx, CSP_EINVAL, "problem too large for one launch");
+    long long smax = 1;
+    for (int k = 1; k < d; ++k) smax *= n;
+    pl.K = pl.g == 1 ? 0 : (int)((smax + pl.c - 1) / pl.c);
+    if (pl.K > KMAX) return fail(ctx, CSP_EINVAL, "problem ranges too thin");
+    pl.lds = lds_bytes_for(pl.c, pl.K, pl.lt);
+    pl.pool = ctx->pool_hint ? ctx->pool_hint * 256ull * pl.g : std::max<unsigned long long>(1ull << 15, 6ull * d * N);
+    const unsigned long long cmaxc = 2ull * d * (unsigned long long)pl.c;
+    pl.ccap = pl.g == 1 ? 1
+                        : std::min<unsigned long long>(cmaxc, ctx->pool_hint ? 64ull
+                                                                             : std::max<unsigned long long>(
+                                                                                   2048, pl.c / 2));
+    return CSP_OK;
 }
 
 void launch_pack(int d, long long n, long long N, const uint8_t *f1, const uint8_t *f2, void *rec, Ctl *ctl,
@@ -1861,7 +2214,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             rc = grow(ctx, &ctx->cand, ctx->cand_cap, (size_t)(2ull * G * NO * ccap), "candidates");
             if (rc) return rc;
             RJ p;
-            fill_job(p, d, n, N, plan, off, f1, f2, A, B, M);
+            fill_job(p, d, n, N, plan, f1, f2, A, B, M);
             p.rec = ctx->rec;
             p.lists = ctx->queue;
             p.pool = ctx->pool;
@@ -2090,32 +2443,16 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
             const int k = lower ? q.d - 1 - dir : dir - q.d;
             pl.off[dir] = lower ? -stride[k] : stride[k];
         }
-        // 16-bit labels when M allows (larger ranges, fewer workgroups per gang)
-        pl.lt = q.M <= 0xFFFFu ? 2 : 4;
-        long long cmax = 0;
-        {
-            long long lo = 1, hi = 1ll << 22;
-            while (lo < hi) {
-                const long long mid = (lo + hi + 1) / 2;
-                if (lds_bytes_for(mid, 0, pl.lt) <= budget) lo = mid;
-                else hi = mid - 1;
-            }
-            cmax = lo;
-        }
-        pl.g = (int)std::min<long long>((N + cmax - 1) / cmax, std::min(ctx->num_cu, GMAX));
-        pl.c = (N + pl.g - 1) / pl.g;
-        if (pl.c > cmax) return fail(ctx, CSP_EINVAL, "batch problem too large for one launch");
-        long long smax = stride[q.d - 1];
-        pl.K = pl.g == 1 ? 0 : (int)((smax + pl.c - 1) / pl.c);
-        if (pl.K > KMAX) return fail(ctx, CSP_EINVAL, "batch problem ranges too thin");
-        pl.lds = lds_bytes_for(pl.c, pl.K, pl.lt);
-        pl.pool = ctx->pool_hint ? ctx->pool_hint * 256ull * pl.g
-                                 : std::max<unsigned long long>(1ull << 15, 6ull * q.d * N);
-        const unsigned long long cmaxc = 2ull * q.d * (unsigned long long)pl.c;
-        pl.ccap = pl.g == 1 ? 1
-                            : std::min<unsigned long long>(cmaxc, ctx->pool_hint ? 64ull
-                                                                                 : std::max<unsigned long long>(
-                                                                                       2048, pl.c / 2));
+        GangPlan gp;
+        rc = plan_gang(ctx, budget, ctx->num_cu, q.d, q.n, N, q.M, gp);
+        if (rc) return rc;
+        pl.c = gp.c;
+        pl.g = gp.g;
+        pl.K = gp.K;
+        pl.lt = gp.lt;
+        pl.lds = gp.lds;
+        pl.pool = gp.pool;
+        pl.ccap = gp.ccap;
         todo[i] = i;
     }
 
@@ -2186,7 +2523,7 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
             lp.lt = pl.lt;
             lp.lds = pl.lds;
             RJ &p = hjobs[j];
-            fill_job(p, q.d, q.n, pl.N, lp, pl.off, q.f1, q.f2, q.A, q.B, q.M);
+            fill_job(p, q.d, q.n, pl.N, lp, q.f1, q.f2, q.A, q.B, q.M);
             p.rec = ctx->arena + pl.off_rec;
             p.lists = reinterpret_cast<unsigned *>(ctx->arena + pl.off_lists);
             p.pool = reinterpret_cast<uint2 *>(ctx->arena + pl.off_pool);
@@ -2296,6 +2633,495 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
     }
     ctx->last_ms = total_ms;
     return CSP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// First-fit allocator over [0, cap) with coalescing, 256-byte granules.
+struct RangeAlloc {
+    std::map<size_t, size_t> free_;     // offset -> length
+    size_t cap = 0;
+    void reset(size_t c)
+    {
+        free_.clear();
+        cap = c;
+        if (c) free_[0] = c;
+    }
+    bool take(size_t len, size_t &off)
+    {
+        len = (len + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                off = it->first;
+                const size_t rest = it->second - len;
+                free_.erase(it);
+                if (rest) free_[off + len] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void give(size_t off, size_t len)
+    {
+        len = (len + 255) & ~(size_t)255;
+        auto it = free_.emplace(off, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct SrvReq {
+    csp_request q;
+    long long N = 0;
+    GangPlan plan;
+    int attempts = 0;
+};
+
+struct SrvAct {
+    SrvReq rq;
+    unsigned long long seq = 0;
+    size_t dev_off = 0, dev_len = 0, path_off = 0, path_len = 0;
+    bool live = false;
+};
+
+struct SrvDone {
+    csp_completion c;
+    std::vector<int64_t> path;
+};
+
+}  // namespace
+
+struct csp_server {
+    csp_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_done = nullptr;
+    bool running = false;
+    bool stop_sent = false;
+    // host-coherent memory shared with the kernel
+    SrvCtl *hctl = nullptr;
+    SJ *hjobs = nullptr;
+    unsigned *hslots = nullptr;
+    Done *hdone = nullptr;
+    long long *hpath = nullptr;
+    size_t path_words = 0;
+    // device memory
+    uint8_t *arena = nullptr;
+    size_t arena_bytes = 0;
+    uint8_t *fixed = nullptr;
+    size_t fixed_bytes = 0;
+    size_t off_state = 0, off_dtail = 0, off_watch = 0, off_out = 0, off_cnt = 0, off_bar = 0, bar_stride = 0;
+    int max_jobs = 0;
+    unsigned ring = 0;
+    int workers = 0;
+    size_t lds = 0;
+    unsigned long long tail = 0, seq = 0, hb = 0;
+    int busy = 0;                       // workgroups the admitted jobs need
+    int active = 0;
+    RangeAlloc dev_alloc, path_alloc;
+    std::deque<SrvReq> pending;
+    std::vector<SrvAct> act;
+    std::vector<int> free_jobs;
+    std::deque<SrvDone> ready;
+    std::vector<SrvDone> handed;        // completions returned by the last poll
+};
+
+namespace {
+
+int srv_fail(csp_server *s, int code, const char *what, hipError_t e = hipSuccess)
+{
+    return fail(s ? s->ctx : nullptr, code, what, e);
+}
+
+size_t srv_footprint(const SrvReq &r)
+{
+    const GangPlan &pl = r.plan;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t NO = 2 * pl.K + 1;
+    return up((size_t)pl.N * rec_bytes(r.q.d)) + up((size_t)pl.g * pl.c * 4) + up((size_t)pl.pool * 8) +
+           up(2ull * pl.g * NO * pl.ccap * 8) + up((size_t)2 * pl.g * NOMAX * 4);
+}
+
+size_t srv_path_words(const SrvReq &r)
+{
+    return r.q.reconstruct ? (size_t)std::min<long long>((long long)r.q.M, r.N) : 1;
+}
+
+// Launch the workers if jobs wait and none run (first use, or after the
+// workers left on stop or a stale heartbeat).
+int srv_ensure_running(csp_server *s)
+{
+    csp_ctx *ctx = s->ctx;
+    if (s->running) {
+        const hipError_t q = hipEventQuery(s->ev_done);
+        if (q == hipSuccess) s->running = false;
+        else if (q != hipErrorNotReady) return srv_fail(s, CSP_EDEVICE, "serving kernel", q);
+    }
+    if (s->running || s->active == 0) return CSP_OK;
+    __atomic_store_n(&s->hctl->stop, 0u, __ATOMIC_RELEASE);
+    s->stop_sent = false;
+    hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(1), 0, s->stream,
+                       reinterpret_cast<unsigned long long *>(s->fixed + s->off_state),
+                       reinterpret_cast<unsigned *>(s->fixed + s->off_watch));
+    ServeArgs a;
+    a.jobs = s->hjobs;
+    a.slots = s->hslots;
+    a.ring = s->ring;
+    a.ctl = s->hctl;
+    a.state = reinterpret_cast<unsigned long long *>(s->fixed + s->off_state);
+    a.dtail = reinterpret_cast<unsigned long long *>(s->fixed + s->off_dtail);
+    a.watch = reinterpret_cast<unsigned *>(s->fixed + s->off_watch);
+    a.stale = ctx->wall_khz * 2000ull;   // 2 s without a heartbeat
+    a.max_jobs = (unsigned)s->max_jobs;
+    hipLaunchKernelGGL(k_serve, dim3(s->workers), dim3(BLOCK), s->lds, s->stream, a);
+    HIP_TRY(hipGetLastError(), "serving launch");
+    HIP_TRY(hipEventRecord(s->ev_done, s->stream), "event");
+    s->running = true;
+    return CSP_OK;
+}
+
+// Admit waiting requests in arrival order while job slots, workers and
+// memory allow.
+int srv_admit(csp_server *s)
+{
+    csp_ctx *ctx = s->ctx;
+    while (!s->pending.empty() && !s->free_jobs.empty()) {
+        SrvReq &r = s->pending.front();
+        if (s->busy + r.plan.g > s->workers) break;
+        const size_t fp = srv_footprint(r), pw = srv_path_words(r);
+        size_t doff = 0, poff = 0;
+        if (!s->dev_alloc.take(fp, doff)) break;
+        if (!s->path_alloc.take(pw * 8, poff)) {
+            s->dev_alloc.give(doff, fp);
+            break;
+        }
+        const int j = s->free_jobs.back();
+        s->free_jobs.pop_back();
+        SJ &sj = s->hjobs[j];
+        SJ w;
+        memset(&w, 0, sizeof(w));
+        LdsPlan lp;
+        lp.ok = true;
+        lp.G = r.plan.g;
+        lp.c = r.plan.c;
+        lp.K = r.plan.K;
+        lp.lt = r.plan.lt;
+        lp.lds = r.plan.lds;
+        fill_job(w.rj, r.q.d, r.q.n, r.N, lp, r.q.f1, r.q.f2, r.q.A, r.q.B, r.q.M);
+        auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        const GangPlan &pl = r.plan;
+        size_t at = doff;
+        w.rj.rec = s->arena + at;
+        at += up((size_t)pl.N * rec_bytes(r.q.d));
+        w.rj.lists = reinterpret_cast<unsigned *>(s->arena + at);
+        at += up((size_t)pl.g * pl.c * 4);
+        w.rj.pool = reinterpret_cast<uint2 *>(s->arena + at);
+        w.rj.pool_flows = pl.pool;
+        at += up((size_t)pl.pool * 8);
+        w.rj.cand = reinterpret_cast<uint2 *>(s->arena + at);
+        w.rj.cand_cap = (unsigned)pl.ccap;
+        at += up(2ull * pl.g * (2 * pl.K + 1) * pl.ccap * 8);
+        w.rj.pubc = reinterpret_cast<unsigned *>(s->arena + at);
+        w.rj.bar = reinterpret_cast<BarHdr *>(s->fixed + s->off_bar + (size_t)j * s->bar_stride);
+        w.rj.out = nullptr;
+        w.rj.labels_out = nullptr;
+        w.rj.max_cycles = 0;
+        w.rj.wait_limit = ctx->wall_khz * 1000ull * 60ull;   // 60 s
+        w.rj.prof = 0;
+        w.out0 = reinterpret_cast<Out *>(s->fixed + s->off_out) + 2 * j;
+        w.outc = w.out0 + 1;
+        w.done_cnt = reinterpret_cast<unsigned *>(s->fixed + s->off_cnt + (size_t)j * 256);
+        w.path = s->hpath + poff / 8;
+        w.path_cap = (long long)pw;
+        w.done = s->hdone + j;
+        w.seq = ++s->seq;
+        w.recon = r.q.reconstruct ? 1 : 0;
+        memcpy(&sj, &w, sizeof(SJ));
+        for (int m = 0; m < pl.g; ++m) {
+            const size_t k = (size_t)((s->tail + (unsigned long long)m) & (s->ring - 1));
+            s->hslots[2 * k] = (unsigned)j;
+            s->hslots[2 * k + 1] = (unsigned)m;
+        }
+        s->tail += (unsigned long long)pl.g;
+        __atomic_store_n(&s->hctl->tail, s->tail, __ATOMIC_RELEASE);
+        SrvAct &a = s->act[j];
+        a.rq = r;
+        a.seq = w.seq;
+        a.dev_off = doff;
+        a.dev_len = fp;
+        a.path_off = poff;
+        a.path_len = pw * 8;
+        a.live = true;
+        s->busy += pl.g;
+        s->active += 1;
+        s->pending.pop_front();
+    }
+    // A request that does not fit even an idle server can never run.
+    if (!s->pending.empty() && s->active == 0) {
+        SrvReq r = s->pending.front();
+        s->pending.pop_front();
+        SrvDone d;
+        memset(&d.c, 0, sizeof(d.c));
+        d.c.tag = r.q.tag;
+        d.c.status = CSP_ENOMEM;
+        d.c.res = csp_result{-1, -1, -1, -1, -1};
+        s->ready.push_back(std::move(d));
+    }
+    return CSP_OK;
+}
+
+void srv_counters(csp_counters &c, const unsigned long long *v)
+{
+    c.C = (int64_t)v[0];
+    c.U = (int64_t)v[1];
+    c.D = (int64_t)v[2];
+    c.E = (int64_t)v[3];
+    c.R = (int64_t)v[4];
+    c.P = (int64_t)v[5];
+    c.I = (int64_t)v[6];
+}
+
+// Collect finished jobs; re-queue those whose wheel overflowed.
+void srv_reap(csp_server *s)
+{
+    std::vector<SrvReq> again;
+    for (int j = 0; j < s->max_jobs; ++j) {
+        SrvAct &a = s->act[j];
+        if (!a.live) continue;
+        if (__atomic_load_n(&s->hdone[j].seq, __ATOMIC_ACQUIRE) != a.seq) continue;
+        const Done &dn = s->hdone[j];
+        const int st = __atomic_load_n(&dn.status, __ATOMIC_ACQUIRE);
+        a.live = false;
+        s->busy -= a.rq.plan.g;
+        s->active -= 1;
+        s->dev_alloc.give(a.dev_off, a.dev_len);
+        if (st == ST_OVERFLOW && a.rq.attempts < 16) {
+            SrvReq r = a.rq;
+            r.attempts += 1;
+            r.plan.pool *= 2;
+            r.plan.ccap = std::min<unsigned long long>(r.plan.ccap * 2, 2ull * r.q.d * r.plan.c);
+            s->path_alloc.give(a.path_off, a.path_len);
+            s->free_jobs.push_back(j);
+            again.push_back(r);
+            continue;
+        }
+        SrvDone d;
+        memset(&d.c, 0, sizeof(d.c));
+        d.c.tag = a.rq.q.tag;
+        d.c.status = st == ST_DONE ? CSP_OK
+                     : st == ST_INVAL ? CSP_EINVAL
+                     : st == ST_OVERFLOW ? CSP_EOVERFLOW
+                     : st == ST_CANCELED ? CSP_ECANCELED
+                                         : CSP_EDEVICE;
+        d.c.res.T = dn.res[0];
+        d.c.res.X = dn.res[1];
+        d.c.res.x = dn.res[2];
+        d.c.res.Y = dn.res[3];
+        d.c.res.F2 = dn.res[4];
+        srv_counters(d.c.cnt, dn.ctr);
+        srv_counters(d.c.cnt_chain, dn.ctr_chain);
+        d.c.solves = dn.solves;
+        if (d.c.status == CSP_OK && a.rq.q.reconstruct && dn.path_len > 0) {
+            const long long *pp = s->hpath + a.path_off / 8;
+            d.path.resize((size_t)dn.path_len);
+            for (long long i = 0; i < dn.path_len; ++i) d.path[(size_t)i] = pp[dn.path_len - 1 - i];
+        }
+        d.c.path_len = (int64_t)d.path.size();
+        s->path_alloc.give(a.path_off, a.path_len);
+        // a gang whose barrier broke leaves its barrier lines dirty: retire the job slot
+        if (st != ST_BROKEN) s->free_jobs.push_back(j);
+        s->ready.push_back(std::move(d));
+    }
+    // overflowed requests go back to the front, in their original order
+    for (auto it = again.rbegin(); it != again.rend(); ++it) s->pending.push_front(*it);
+}
+
+}  // namespace
+
+extern "C" {
+
+int csp_serve_open(csp_ctx *ctx, uint64_t arena_bytes, int max_jobs, csp_server **out)
+{
+    if (!ctx || !out || max_jobs < 1 || max_jobs > 4096 || arena_bytes < (1u << 20))
+        return fail(ctx, CSP_EINVAL, "serve_open arguments");
+    *out = nullptr;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    csp_server *s = new csp_server;
+    s->ctx = ctx;
+    auto bail = [&](int code, const char *what, hipError_t e) {
+        (void)csp_serve_close(s);
+        return fail(ctx, code, what, e);
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
+        return bail(CSP_EDEVICE, "serve stream", e);
+    if ((e = hipEventCreateWithFlags(&s->ev_done, hipEventDisableTiming)) != hipSuccess)
+        return bail(CSP_EDEVICE, "serve event", e);
+    const void *kf = (const void *)k_serve;
+    s->lds = ctx->lds_limit > 4096 ? ctx->lds_limit - 4096 : 0;
+    if ((e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s->lds)) != hipSuccess)
+        return bail(CSP_EDEVICE, "serve LDS attribute", e);
+    int nb = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kf, BLOCK, s->lds)) != hipSuccess || nb < 1)
+        return bail(CSP_EDEVICE, "serve occupancy", e);
+    s->workers = std::min(nb * ctx->num_cu, GMAX);
+    s->max_jobs = max_jobs;
+    s->ring = 1;
+    while (s->ring < 2u * (unsigned)s->workers) s->ring <<= 1;
+    // host-coherent tables
+    const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+    s->path_words = std::max<size_t>(1u << 16, (size_t)max_jobs * 8192);
+    if ((e = hipHostMalloc((void **)&s->hctl, sizeof(SrvCtl), fl)) != hipSuccess) return bail(CSP_ENOMEM, "serve control", e);
+    if ((e = hipHostMalloc((void **)&s->hjobs, sizeof(SJ) * max_jobs, fl)) != hipSuccess) return bail(CSP_ENOMEM, "serve jobs", e);
+    if ((e = hipHostMalloc((void **)&s->hslots, 8ull * s->ring, fl)) != hipSuccess) return bail(CSP_ENOMEM, "serve slots", e);
+    if ((e = hipHostMalloc((void **)&s->hdone, sizeof(Done) * max_jobs, fl)) != hipSuccess) return bail(CSP_ENOMEM, "serve results", e);
+    if ((e = hipHostMalloc((void **)&s->hpath, 8ull * s->path_words, fl)) != hipSuccess) return bail(CSP_ENOMEM, "serve paths", e);
+    memset(s->hctl, 0, sizeof(SrvCtl));
+    memset(s->hjobs, 0, sizeof(SJ) * max_jobs);
+    memset(s->hslots, 0, 8ull * s->ring);
+    memset(s->hdone, 0, sizeof(Done) * max_jobs);
+    // device: control words, per-job outputs, finish counters and barriers
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t at = 0;
+    s->off_state = at;
+    at += 256;
+    s->off_dtail = at;
+    at += 256;
+    s->off_watch = at;
+    at += 256;
+    s->off_out = at;
+    at = up(at + 2 * sizeof(Out) * max_jobs);
+    s->off_cnt = at;
+    at = up(at + 256ull * max_jobs);
+    s->bar_stride = up(bar_bytes(GMAX));
+    s->off_bar = at;
+    at += s->bar_stride * max_jobs;
+    s->fixed_bytes = at;
+    if ((e = hipMalloc((void **)&s->fixed, s->fixed_bytes)) != hipSuccess) return bail(CSP_ENOMEM, "serve tables", e);
+    if ((e = hipMalloc((void **)&s->arena, arena_bytes)) != hipSuccess) return bail(CSP_ENOMEM, "serve arena", e);
+    s->arena_bytes = arena_bytes;
+    {
+        const unsigned long long words = s->fixed_bytes / 4;
+        const int nbz = (int)std::max(1ull, std::min((words + 255) / 256, 4096ull));
+        hipLaunchKernelGGL(k_zero, dim3(nbz), dim3(256), 0, s->stream, reinterpret_cast<unsigned *>(s->fixed), words);
+        if ((e = hipGetLastError()) != hipSuccess) return bail(CSP_EDEVICE, "serve zero", e);
+        if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return bail(CSP_EDEVICE, "serve zero", e);
+    }
+    s->dev_alloc.reset(arena_bytes & ~(size_t)255);
+    s->path_alloc.reset(8ull * s->path_words);
+    s->act.resize(max_jobs);
+    for (int j = max_jobs - 1; j >= 0; --j) s->free_jobs.push_back(j);
+    *out = s;
+    return CSP_OK;
+}
+
+int csp_serve_submit(csp_server *s, const csp_request *req)
+{
+    if (!s || !req) return CSP_EINVAL;
+    csp_ctx *ctx = s->ctx;
+    const csp_request &q = *req;
+    if (!q.f1 || !q.f2 || !q.A || !q.B) return fail(ctx, CSP_EINVAL, "null argument in request");
+    SrvReq r;
+    r.q = q;
+    r.q.reconstruct = q.reconstruct ? 1 : 0;
+    int rc = check_shape(ctx, q.d, q.n, q.M, r.N);
+    if (rc) return rc;
+    rc = plan_gang(ctx, s->lds, s->workers, q.d, q.n, r.N, q.M, r.plan);
+    if (rc) return rc;
+    if (srv_footprint(r) > s->dev_alloc.cap) return fail(ctx, CSP_ENOMEM, "request larger than the serving arena");
+    if (srv_path_words(r) * 8 > s->path_alloc.cap) return fail(ctx, CSP_ENOMEM, "path longer than the path pool");
+    if (s->stop_sent) {
+        // the workers were told to leave when idle; keep them
+        __atomic_store_n(&s->hctl->stop, 0u, __ATOMIC_RELEASE);
+        s->stop_sent = false;
+    }
+    s->pending.push_back(r);
+    rc = srv_admit(s);
+    if (rc) return rc;
+    return srv_ensure_running(s);
+}
+
+int csp_serve_poll(csp_server *s, csp_completion *out, int cap, int *count)
+{
+    if (!s || !count || cap < 0 || (cap > 0 && !out)) return CSP_EINVAL;
+    *count = 0;
+    s->handed.clear();
+    __atomic_store_n(&s->hctl->heartbeat, ++s->hb, __ATOMIC_RELEASE);
+    srv_reap(s);
+    int rc = srv_admit(s);
+    if (rc) return rc;
+    rc = srv_ensure_running(s);
+    if (rc) return rc;
+    if (s->running && s->active == 0 && s->pending.empty() && !s->stop_sent) {
+        // idle: let the workers leave so the GPU is free for other work
+        __atomic_store_n(&s->hctl->stop, 1u, __ATOMIC_RELEASE);
+        s->stop_sent = true;
+    }
+    while (*count < cap && !s->ready.empty()) {
+        s->handed.push_back(std::move(s->ready.front()));
+        s->ready.pop_front();
+        SrvDone &d = s->handed.back();
+        d.c.path = d.path.empty() ? nullptr : d.path.data();
+        out[(*count)++] = d.c;
+    }
+    return CSP_OK;
+}
+
+int csp_serve_pending(const csp_server *s, int *queued, int *running)
+{
+    if (!s) return CSP_EINVAL;
+    if (queued) *queued = (int)s->pending.size() + (int)s->ready.size();
+    if (running) *running = s->active;
+    return CSP_OK;
+}
+
+int csp_serve_close(csp_server *s)
+{
+    if (!s) return CSP_OK;
+    int rc = CSP_OK;
+    if (s->hctl && s->ev_done && s->stream) {
+        // finish admitted work (requests not yet admitted are dropped), then
+        // let the workers leave
+        s->pending.clear();
+        while (s->active > 0) {
+            __atomic_store_n(&s->hctl->heartbeat, ++s->hb, __ATOMIC_RELEASE);
+            srv_reap(s);
+            if (srv_ensure_running(s) != CSP_OK) {
+                rc = CSP_EDEVICE;
+                break;
+            }
+        }
+        __atomic_store_n(&s->hctl->stop, 1u, __ATOMIC_RELEASE);
+        if (s->running && hipEventSynchronize(s->ev_done) != hipSuccess) rc = CSP_EDEVICE;
+        s->running = false;
+    }
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->ev_done) (void)hipEventDestroy(s->ev_done);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->arena) (void)hipFree(s->arena);
+    if (s->fixed) (void)hipFree(s->fixed);
+    if (s->hctl) (void)hipHostFree(s->hctl);
+    if (s->hjobs) (void)hipHostFree(s->hjobs);
+    if (s->hslots) (void)hipHostFree(s->hslots);
+    if (s->hdone) (void)hipHostFree(s->hdone);
+    if (s->hpath) (void)hipHostFree(s->hpath);
+    delete s;
+    return rc;
 }
 
 int csp_set_path(csp_ctx *ctx, int path)

@@ -50,3 +50,29 @@ def test_product_path_has_no_oracle_dependency():
                 if f.endswith((".py", ".hip", ".h", ".cpp")):
                     text = open(os.path.join(dirpath, f)).read()
                     assert not pat.search(text), os.path.join(dirpath, f)
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Sizes and field offsets of every struct the binding mirrors, as the C
+    compiler lays them out from the header."""
+    import subprocess
+    from paper_1511_06441_amd import csp
+    structs = {"csp_result": csp.csp_result, "csp_counters": csp.csp_counters,
+               "csp_problem": csp.csp_problem, "csp_request": csp.csp_request,
+               "csp_completion": csp.csp_completion}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "csp.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)

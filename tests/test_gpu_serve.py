@@ -1,0 +1,181 @@
+"""Serving with continuous batching: requests submitted while others run
+give the oracle's result and path, and the same completion alone and in the
+mix."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1511_06441_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def solver(torch):
+    from paper_1511_06441_amd import csp
+    s = csp.Solver(0)
+    yield s
+    s.close()
+
+
+@pytest.fixture
+def server(solver):
+    from paper_1511_06441_amd import csp
+    srv = csp.Server(solver, arena_bytes=4 << 30, max_jobs=64)
+    yield srv
+    srv.close()
+
+
+def _oracle_request(inst):
+    from oracle import oracle as O
+    ref = O.solve_instance(inst, want_labels=False)
+    path, res, _ = O.reconstruct(inst.d, inst.n, inst.f1, inst.f2, inst.A, inst.B, inst.M)
+    assert res.tuple() == ref.tuple()
+    return ref, [int(v) for v in path]
+
+
+def _key(c):
+    return (c.status, c.res, tuple(sorted(c.counters.items())), c.solves, tuple(c.path))
+
+
+def _run_all(server, devs, recon=True, stagger=0):
+    """Submit every request (every `stagger`-th one after a poll, so later
+    requests arrive while earlier ones run) and collect the completions."""
+    done = {}
+    for k, di in enumerate(devs):
+        server.submit(di, reconstruct=recon, tag=k)
+        if stagger and k % stagger == stagger - 1:
+            for c in server.poll():
+                done[c.tag] = c
+    for c in server.drain():
+        done[c.tag] = c
+    assert sorted(done) == list(range(len(devs)))
+    return done
+
+
+def test_serve_small_vs_oracle(server, torch):
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(51, j, lo2=(8, 48), lo3=(4, 16)) for j in range(24)]
+    devs = [csp.to_device(i) for i in insts]
+    _say("serving 24 small requests")
+    done = _run_all(server, devs, stagger=5)
+    for k, inst in enumerate(insts):
+        ref, path = _oracle_request(inst)
+        c = done[k]
+        assert c.status == 0, (inst.name, c.status)
+        assert c.res == ref.tuple(), inst.name
+        assert c.counters == ref.counters, inst.name
+        assert c.path == path, inst.name
+        assert c.solves == (max(len(path) - 1, 1) if ref.T >= 0 else 1)
+
+
+def test_serve_gangs_vs_plain(server, solver, torch):
+    """Requests that need gangs of workgroups, mixed with small ones: each
+    completion equals the plain solve and reconstruction of the request."""
+    from paper_1511_06441_amd import csp
+    insts = [gen.opposite_faces(2, 420, 3, 9, 9, 3000), gen.square64(1),
+             gen.opposite_faces(3, 52, 4, 12, 12, 600), gen.square64(2),
+             gen.opposite_faces(2, 300, 5, 4, 4, 1200), gen.opposite_faces(3, 20, 6, 7, 7, 160)]
+    devs = [csp.to_device(i) for i in insts]
+    _say("serving gang requests")
+    done = _run_all(server, devs, stagger=2)
+    for k, (inst, di) in enumerate(zip(insts, devs)):
+        r1, c1 = solver.solve(di)
+        scratch = torch.zeros(inst.N, dtype=torch.uint8, device="cuda")
+        path, res = solver.reconstruct(di, scratch)
+        c = done[k]
+        assert c.status == 0, (k, c.status)
+        assert c.res == r1.tuple() == res.tuple(), k
+        assert c.counters == c1.asdict(), k
+        assert c.path == path.tolist(), k
+
+
+def test_serve_alone_equals_mix(server, torch):
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(51, j, lo2=(16, 160), lo3=(8, 32)) for j in range(16)]
+    devs = [csp.to_device(i) for i in insts]
+    alone = {}
+    for k, di in enumerate(devs):
+        server.submit(di, reconstruct=True, tag=k)
+        for c in server.drain():
+            alone[c.tag] = c
+    mixed = _run_all(server, devs, stagger=3)
+    for k in range(len(devs)):
+        assert _key(alone[k]) == _key(mixed[k]), insts[k].name
+
+
+def test_serve_without_reconstruction(server, torch):
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(53, j, lo2=(8, 64), lo3=(4, 20)) for j in range(12)]
+    done = _run_all(server, [csp.to_device(i) for i in insts], recon=False)
+    for k, inst in enumerate(insts):
+        ref = O.solve_instance(inst, want_labels=False)
+        assert done[k].res == ref.tuple() and done[k].counters == ref.counters
+        assert done[k].path == [] and done[k].solves == 1
+
+
+def test_serve_overflow_retry(solver, torch):
+    """A one-flow starting wheel forces re-admission with larger pools."""
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(7, j, lo2=(8, 64), lo3=(4, 20)) for j in range(8)]
+    csp.csp_set_pool_hint(solver.ctx, 1)
+    try:
+        srv = csp.Server(solver, arena_bytes=1 << 30, max_jobs=16)
+        try:
+            done = _run_all(srv, [csp.to_device(i) for i in insts])
+        finally:
+            srv.close()
+    finally:
+        csp.csp_set_pool_hint(solver.ctx, 0)
+    for k, inst in enumerate(insts):
+        ref, path = _oracle_request(inst)
+        assert done[k].status == 0 and done[k].res == ref.tuple() and done[k].path == path
+
+
+def test_serve_errors_come_back_per_request(server, torch):
+    from paper_1511_06441_amd import csp
+    ok = gen.square64(3)
+    bad = gen.square64(3)
+    bad.B = bad.B.copy()
+    bad.B[0] = 1                      # vertex 0 is in A too
+    zero = gen.square64(3)
+    zero.f1 = zero.f1.copy()
+    zero.f1[5] = 0                    # a real edge with f1 = 0
+    done = _run_all(server, [csp.to_device(i) for i in (ok, bad, zero)])
+    assert done[0].status == csp.CSP_OK
+    assert done[1].status == csp.CSP_EINVAL
+    assert done[2].status == csp.CSP_EINVAL
+    with pytest.raises(csp.CspError):
+        server.submit(csp.DeviceInstance(2, 1, ok_t := torch.zeros(4, dtype=torch.uint8, device="cuda"),
+                                         ok_t, ok_t, ok_t, 10))
+
+
+def test_serve_idle_then_again(server, torch):
+    """Workers leave when the server idles; the next request starts them again."""
+    from paper_1511_06441_amd import csp
+    inst = gen.square64(1)
+    ref, path = _oracle_request(inst)
+    di = csp.to_device(inst)
+    for rep in range(3):
+        server.submit(di, tag=rep)
+        (c,) = server.drain()
+        assert c.res == ref.tuple() and c.path == path
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.05:
+            server.poll()
+            time.sleep(0.005)
