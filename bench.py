@@ -143,7 +143,11 @@ def run_serve(args):
     # warm-up: the smallest request
     small = min(range(count), key=lambda k: dev[k].N)
     serving.replay(server, [dev[small]])
-    sat = serving.replay(server, dev)
+
+    def report(done, submitted, secs):
+        print(f"#   {done}/{submitted} done after {secs:.0f} s", file=sys.stderr, flush=True)
+
+    sat = serving.replay(server, dev, progress=report)
     sat_rps = count / sat.makespan
     solves = sum(c.solves for c in sat.completions.values())
     R = sum(c.counters["R"] + c.chain_counters["R"] for c in sat.completions.values())
@@ -151,7 +155,7 @@ def run_serve(args):
     sweep = []
     for frac in args.serve_fracs:
         arr = gen.poisson_arrivals(count, frac * sat_rps, 52)
-        tr = serving.replay(server, dev, arr)
+        tr = serving.replay(server, dev, arr, progress=report)
         same = all(tr.completions[k].res == sat.completions[k].res and
                    tr.completions[k].path == sat.completions[k].path for k in range(count))
         sweep.append({"qps": frac * sat_rps, "fraction_of_saturation": frac,
@@ -176,6 +180,7 @@ def run_serve(args):
         t0 = time.perf_counter()
         same = True
         for k, di in enumerate(dev):
+            print(f"#   plain request {k}", file=sys.stderr, flush=True)
             scratch = torch.zeros(di.N, dtype=torch.uint8, device="cuda")
             path, res = solver.reconstruct(di, scratch)
             c = sat.completions[k]

@@ -7,47 +7,45 @@
 // source, state) plus a separate phantom list and runs nine barrier-separated
 // steps per time unit.  Here every unit of water in transit is a flow record
 // (destination, quality, arriving direction) filed in a timing wheel by its
-// arrival time, so regular and phantom edges are the same thing and a cycle
-// is two phases:
+// arrival time, so regular and phantom edges are the same thing, and Step 1's
+// time skip is the first non-empty bucket after t.  A cycle is:
 //
-//   arrival   (Steps 1-3, 8): deliver the bucket of time t; atomicMax the
-//             quality into the destination's label; the first thread that
-//             raises a label this cycle appends the vertex to the improved
-//             set I_t.  A vertex of B in I_t ends the run (Step 6).
+//   arrival   (Steps 1-3, 8): deliver the bucket of time t; raise each
+//             destination's label to the best quality delivered; the vertices
+//             whose label rose form the improved set I_t.  A vertex of B in
+//             I_t ends the run (Step 6).
 //   departure (Steps 4-5): every Q in I_t tests its 2d lattice neighbours;
 //             if Label(Q) - f2 > Label(P), a flow (P, Label(Q) - f2) is filed
 //             in bucket (t + f1) mod W.  Delivered flows simply leave their
 //             bucket (Steps 7, 9).
 //
-// Step 1's time skip is the first non-empty bucket after t.
+// Two single-solve kernels, chosen per problem:
 //
-// Layout and synchronisation, chosen for the cost profile of MI355X (device
-// atomics on one address serialise at ~11 ns each; a grid-wide barrier costs
-// microseconds and grows with the number of participants):
+//  * k_ranges (range-owned, the usual one).  The lattice is cut into g
+//    contiguous index ranges, one per workgroup; ranges of one XCD are
+//    contiguous.  A workgroup keeps its range's labels (16 or 32 bits), the
+//    frontier bitmap, the B bitmap and the wheel fill counts in LDS and owns
+//    its own wheel in HBM, so every label test, delivery and commit is an
+//    LDS operation and the wheel needs no device-wide counter.  A neighbour
+//    test whose target lies in another range is shipped to the owner as a
+//    candidate (local index, f1, direction, quality) and tested there after
+//    the next barrier against labels that are still those of the sending
+//    time.  One combining barrier per cycle (a two-level tree, one group per
+//    XCD, one release line per member) returns the next event time, flags,
+//    counts and the best B key.
+//  * k_solve (global labels, for lattices whose ranges do not fit LDS).
+//    Label words in HBM pack (label << 2) | inB << 1 | idle; a delivery is one
+//    atomicMax that raises the label and elects the first improver; frontier
+//    segments are balanced by an LDS prefix sum; two grid barriers per cycle.
 //
-//  * One persistent cooperative kernel, one 1024-thread workgroup per CU.
-//  * Each workgroup owns a private segment of every wheel bucket and fills it
-//    with LDS counters; it later delivers exactly the flows it filed, so the
-//    wheel needs no device-wide counter at all.
-//  * Each workgroup appends the vertices it improved to a private frontier
-//    segment.  After the arrival barrier every workgroup reads all segment
-//    sizes, prefix-sums them in LDS and departs an equal slice of the
-//    concatenation, so the departure work is balanced every cycle.
-//  * The next event time is the minimum of per-workgroup minima published
-//    before the departure barrier.
-//  * The grid barrier is a two-level counter tree (one group per XCD) with
-//    one release flag per workgroup, so no address sees more than ~32 atomics
-//    and every waiter spins on its own cache line.
-//  * Label words pack (label << 2) | inB << 1 | idle.  idle = 1 means "not yet
-//    in this cycle's improved set".  A delivery does atomicMax(word, q << 2),
-//    which raises the label and clears idle and inB at once; the returned old
-//    word says whether this thread raised the label first this cycle and
-//    whether the vertex is in B.  Departure writes the word back with both
-//    bits restored.
-//  * Edge times are repacked per vertex: record v holds (f1, f2) of its 2d
-//    incident edges in direction order (zero where the lattice ends), so a
-//    departure reads one 4/8/16-byte record instead of 4d scattered bytes and
-//    needs no coordinate arithmetic.
+// k_batch runs many range-owned solves in one persistent launch (a gang of
+// workgroups per problem) and k_serve keeps such workers alive while a host
+// feeds them requests, including the reconstruction chain of section 2.
+//
+// Measured on MI355X, and the reason for the shapes above: device atomics on
+// one address serialise at ~11 ns each; scattered atomicMax reaches ~27 G/s;
+// a grid barrier costs several microseconds and grows with the number of
+// participants and with the dirty data each must write back.
 //
 // All arithmetic is integer; results are bit-identical to the CPU oracle.
 
@@ -1012,14 +1010,19 @@ struct RunRes {
     int found;
     long long t;
     unsigned X, LX, yd;
+    unsigned mf;                   // largest f1 of the lattice
 };
 
 // M and B of the solve are arguments so that a chain of solves on one
 // lattice (reconstruction) can change them: B is the mask p.B, or the single
 // vertex bvert when bvert >= 0.  epoch continues over the gang's barriers.
+// abits (nullable, [g][cw] words) keeps the A bitmap of each range: a full
+// initialisation (reinit_mf == 0) writes it; a later solve of the same
+// lattice passes the largest f1 seen before as reinit_mf and starts from
+// abits, without re-reading or re-packing the edges.
 template <int D>
 __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M, long long bvert, unsigned &epoch,
-                            Out *out)
+                            Out *out, unsigned *abits = nullptr, unsigned reinit_mf = 0)
 {
     using RT = typename Rec<D>::T;
     __shared__ unsigned s_wave[NWAVES];
@@ -1095,7 +1098,24 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
 
     // ---- Initialization (Algorithm 3): pack and check the range's edges;
     // Label = M on A, 0 elsewhere; A is I_0.
-    {
+    if (reinit_mf) {
+        for (unsigned w = tid; w < cw; w += BLOCK) {
+            unsigned bits = abits[(unsigned long long)r * cw + w];
+            fb[w] = bits;
+            while (bits) {
+                const unsigned bt = (unsigned)(__ffs(bits) - 1);
+                bits &= bits - 1u;
+                lset(lab, l16, w * 32u + bt, M);
+            }
+        }
+        if (tid == 0) {
+            s_mf = reinit_mf;
+            if (bvert >= base && bvert < base + (long long)cr) {
+                const unsigned i = (unsigned)(bvert - base);
+                bb[i >> 5] |= 1u << (i & 31);
+            }
+        }
+    } else {
         unsigned mf = 0, bad = 0;
         long long stride[D];
         {
@@ -1160,6 +1180,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         }
     }
     __syncthreads();
+    if (abits && !reinit_mf) {
+        for (unsigned w = tid; w < cw; w += BLOCK) abits[(unsigned long long)r * cw + w] = fb[w];
+    }
 
     // Frontier bitmap -> sorted list of local indices; clear the bitmap;
     // best (label, -index) over the B members in it.
@@ -1207,6 +1230,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
 
     int status = ST_RUNNING;
     unsigned W = 2;
+    RunRes rr;
     {
         Comb mine, all;
         mine.mn = 0xFFFFFFFFu;
@@ -1216,6 +1240,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all)) status = ST_BROKEN;
         else if (all.orf & (SF_BAD | SF_INVAL)) status = ST_INVAL;
         while (W <= (unsigned)all.mx) W <<= 1;
+        rr.mf = (unsigned)all.mx;
         if (tid == 0) s_flags = 0;                   // an A member of B is an error, not a hit
         __syncthreads();
     }
@@ -1224,7 +1249,6 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     const unsigned CS = p.cand_cap;
     uint2 *wheel = p.pool + (unsigned long long)r * W * S;
 
-    RunRes rr;
     rr.X = rr.LX = 0;
     long long t = 0, t_prev = 0;
     unsigned cyc = 0, par = 0;
@@ -1567,6 +1591,7 @@ struct SJ {
     unsigned *done_cnt;                // members finished (zero between jobs)
     long long *path;                   // host-coherent; X, Y, Y', ... until A
     long long path_cap;
+    unsigned *abits;                   // [g][cw] A bitmap of each range
     Done *done;                        // host-coherent
     unsigned long long seq;
     int recon;
@@ -1690,9 +1715,10 @@ __device__ __forceinline__ void serve_job(const SJ &sj, unsigned r, unsigned *sm
     int status = ST_DONE;
     long long plen = 0, solves = 0;
     long long X = -1, T = 0, F2 = 0, bvert = -1;
-    unsigned Mc = p.M, f1x = 0, f2x = 0;
+    unsigned Mc = p.M, f1x = 0, f2x = 0, mf = 0;
     for (;;) {
-        const RunRes rr = range_run<D>(p, r, smem, Mc, bvert, epoch, solves ? sj.outc : sj.out0);
+        const RunRes rr = range_run<D>(p, r, smem, Mc, bvert, epoch, solves ? sj.outc : sj.out0, sj.abits, mf);
+        mf = rr.mf;
         if (rr.status != ST_DONE) { status = rr.status; break; }
         if (solves == 0) {
             if (!rr.found || !sj.recon) break;
@@ -2754,7 +2780,8 @@ size_t srv_footprint(const SrvReq &r)
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t NO = 2 * pl.K + 1;
     return up((size_t)pl.N * rec_bytes(r.q.d)) + up((size_t)pl.g * pl.c * 4) + up((size_t)pl.pool * 8) +
-           up(2ull * pl.g * NO * pl.ccap * 8) + up((size_t)2 * pl.g * NOMAX * 4);
+           up(2ull * pl.g * NO * pl.ccap * 8) + up((size_t)2 * pl.g * NOMAX * 4) +
+           up((size_t)pl.g * ((pl.c + 31) / 32) * 4);
 }
 
 size_t srv_path_words(const SrvReq &r)
@@ -2837,6 +2864,8 @@ int srv_admit(csp_server *s)
         w.rj.cand_cap = (unsigned)pl.ccap;
         at += up(2ull * pl.g * (2 * pl.K + 1) * pl.ccap * 8);
         w.rj.pubc = reinterpret_cast<unsigned *>(s->arena + at);
+        at += up((size_t)2 * pl.g * NOMAX * 4);
+        w.abits = reinterpret_cast<unsigned *>(s->arena + at);
         w.rj.bar = reinterpret_cast<BarHdr *>(s->fixed + s->off_bar + (size_t)j * s->bar_stride);
         w.rj.out = nullptr;
         w.rj.labels_out = nullptr;

@@ -31,9 +31,11 @@ class Trace:
         return float(self.finished.max() - self.arrival.min()) if len(self.finished) else 0.0
 
 
-def replay(server, devs, arrivals=None, reconstruct=True, timeout_s=600.0, nap_s=0.0002) -> Trace:
+def replay(server, devs, arrivals=None, reconstruct=True, timeout_s=600.0, nap_s=0.0002,
+           progress=None, progress_every_s=15.0) -> Trace:
     """Submit request k at arrivals[k] seconds after the start (all at once
-    when arrivals is None) and poll until every request has completed."""
+    when arrivals is None) and poll until every request has completed.
+    progress(done, submitted, seconds) is called every progress_every_s."""
     count = len(devs)
     arr = np.zeros(count) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
     sub = np.full(count, np.nan)
@@ -41,8 +43,12 @@ def replay(server, devs, arrivals=None, reconstruct=True, timeout_s=600.0, nap_s
     comps = {}
     nxt = 0
     t0 = time.perf_counter()
+    t_report = progress_every_s
     while len(comps) < count:
         now = time.perf_counter() - t0
+        if progress is not None and now >= t_report:
+            progress(len(comps), nxt, now)
+            t_report += progress_every_s
         while nxt < count and arr[nxt] <= now:
             server.submit(devs[nxt], reconstruct=reconstruct, tag=nxt)
             sub[nxt] = time.perf_counter() - t0
