@@ -41,6 +41,11 @@ WORKLOADS = {
                           build=lambda gen: [gen.cube256_stress(22)], sample_index=None),
     "square64": dict(desc="d=2 n=64, f1,f2 iid U{1..5} seed 1, columns x=0 -> x=63, M=200",
                      build=lambda gen: [gen.square64(1)], sample_index=0),
+    "paper_cubes": dict(desc="the paper's runs (section 8): d=3 cubes n=50,75,100,125, water on the cube "
+                             "boundary, B the centre vertex, f1,f2 iid U{1..100} seed 61, M=10000",
+                        build=lambda gen: [gen.cube_boundary_to_center(n, 61, K=100, M=10000)
+                                           for n in (50, 75, 100, 125)],
+                        sample_index=3),
 }
 
 BATCH_DESC = ("1,024 independent problems (master seed 41): d in {2,3}, side log-uniform in [32,512] (d=2) / "
@@ -289,6 +294,7 @@ def main():
                    "parallelism": "single GPU"},
         "solves_per_s": solves / wall,
         "results": [dict(T=r.T, X=r.X, x=r.x, Y=r.Y, F2=r.F2, **c.asdict()) for r, c, _ in runs[0]],
+        "kernel_ms_per_solve": [round(sum(st[k][2] for st in runs) / len(runs), 3) for k in range(len(dev))],
         "roofline": {
             "bound": "hbm",
             "kernel": (f"k_ranges<{insts[0].d}>" if csp.csp_last_path(solver.ctx) == 1

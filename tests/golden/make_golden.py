@@ -32,6 +32,9 @@ def cases():
             out[f"cube128_s{s}_M{M}"] = lambda s=s, M=M: gen.cube128(s, M)
     out["cube256_s21"] = lambda: gen.cube256(21)
     out["cube256stress_s22"] = lambda: gen.cube256_stress(22)
+    # the paper's own shape (section 8): water on the cube boundary, B the centre
+    for n in (50, 75, 100, 125):
+        out[f"paper{n}_s61"] = lambda n=n: gen.cube_boundary_to_center(n, 61, K=100, M=10000)
     return out
 
 

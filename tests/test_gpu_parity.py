@@ -170,8 +170,9 @@ def test_empty_A(solver, torch):
 
 def _golden_cases():
     out = []
-    for f in sorted(glob.glob(os.path.join(GOLDEN, "cube*.json"))):
-        out.append(os.path.basename(f)[:-5])
+    for pat in ("cube*.json", "paper*.json"):
+        for f in sorted(glob.glob(os.path.join(GOLDEN, pat))):
+            out.append(os.path.basename(f)[:-5])
     return out
 
 
@@ -183,6 +184,8 @@ def _build(rec):
         return gen.cube256_stress(rec["meta"]["seed"], rec["M"])
     if nm.startswith("cube256"):
         return gen.cube256(rec["meta"]["seed"], rec["M"])
+    if nm.startswith("paper"):
+        return gen.cube_boundary_to_center(rec["n"], rec["meta"]["seed"], K=rec["meta"]["K1"], M=rec["M"])
     raise KeyError(nm)
 
 
