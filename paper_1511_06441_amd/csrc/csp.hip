@@ -93,6 +93,7 @@ struct BarHdr {
     unsigned grp[NGRP][32];        // group counters, one per 128-byte line
     unsigned root[32];
     unsigned long long gslot[NGRP][16];
+    unsigned long long res[2][16]; // sums and maximum of the last two barriers
     int broken;
     int pad[31];
 };
@@ -738,11 +739,14 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
 constexpr int KMAX = 4;                 // neighbours lie within KMAX ranges
 constexpr int NOMAX = 2 * KMAX + 1;
 
+// What a gang barrier combines.  mn is below 0xFFFF or 0xFFFFFFFF (none);
+// only the top four bits of orf are combined.
 struct Comb {
     unsigned mn;                        // minimum (0xFFFFFFFF = none)
-    unsigned orf;                       // bitwise or
+    unsigned orf;                       // bitwise or (bits 28-31)
     unsigned long long s0, s1, s2;      // sums
     unsigned long long mx;              // maximum
+    const unsigned long long *rest;     // where s0, s1, s2, mx of this barrier lie (null: in the fields)
 };
 
 __device__ __forceinline__ unsigned long long *bar_slot(BarHdr *b, unsigned i)
@@ -790,7 +794,7 @@ __device__ __forceinline__ void comb_wave(unsigned &mn, unsigned &orf, unsigned 
 // wait that outlasts `limit` wall-clock ticks marks the gang broken and the
 // call returns false, so a logic error drains the gang instead of hanging.
 __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
-                             const Comb &mine, Comb &out)
+                             const Comb &mine, Comb &out, bool need_rest)
 {
     __shared__ int s_ok;
     __shared__ unsigned long long s_o[5];
@@ -798,6 +802,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
     ++epoch;
     if (g == 1) {
         out = mine;
+        out.rest = nullptr;
         return true;
     }
     if (threadIdx.x < 64) {
@@ -867,24 +872,27 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
                     mx = ld64(&gs[4]);
                 }
                 comb_wave(mn, orf, s0, s1, s2, mx);
-                const unsigned long long w0 = (unsigned long long)mn | ((unsigned long long)orf << 32);
-                for (unsigned i = lane; i < g; i += 64) {
-                    unsigned long long *fl = bar_flag(bh, g, i);
-                    st64(&fl[1], w0);
-                    st64(&fl[2], s0);
-                    st64(&fl[3], s1);
-                    st64(&fl[4], s2);
-                    st64(&fl[5], mx);
+                // sums and maximum once per gang; the release word of every
+                // member carries the epoch, the flags and the minimum
+                unsigned long long *rs = bh->res[epoch & 1];
+                if (lane == 0) {
+                    st64(&rs[0], s0);
+                    st64(&rs[1], s1);
+                    st64(&rs[2], s2);
+                    st64(&rs[3], mx);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], (unsigned long long)epoch);
+                const unsigned long long w = ((unsigned long long)epoch << 32) |
+                                             ((unsigned long long)(orf >> 28) << 16) | (mn < 0xFFFFu ? mn : 0xFFFFu);
+                for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], w);
             }
         }
         if (lane == 0) {
             int ok = 1;
             unsigned long long *fl = bar_flag(bh, g, m);
             const unsigned long long t0 = wall_clock64();
-            while (ld64(&fl[0]) < (unsigned long long)epoch) {
+            unsigned long long w;
+            while (((w = ld64(&fl[0])) >> 32) < (unsigned long long)epoch) {
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > limit) {
                     __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -894,7 +902,12 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-            for (int k = 0; k < 5; ++k) s_o[k] = ld64(&fl[1 + k]);
+            const unsigned mn16 = (unsigned)(w & 0xFFFFu), orf = (unsigned)((w >> 16) & 0xFu) << 28;
+            s_o[0] = (unsigned long long)(mn16 == 0xFFFFu ? 0xFFFFFFFFu : mn16) | ((unsigned long long)orf << 32);
+            if (need_rest || (orf & SF_BHIT)) {
+                const unsigned long long *rs = bh->res[epoch & 1];
+                for (int k = 0; k < 4; ++k) s_o[1 + k] = ld64(&rs[k]);
+            }
             s_ok = ok;
         }
     }
@@ -905,6 +918,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
     out.s1 = s_o[2];
     out.s2 = s_o[3];
     out.mx = s_o[4];
+    out.rest = bh->res[epoch & 1];
     const bool ok = s_ok != 0;
     __syncthreads();
     return ok;
@@ -927,13 +941,14 @@ struct RJ {
     int d;
     int K;                         // neighbours lie within K ranges
     int lt;                        // LDS label bytes (2 or 4)
+    int llist;                     // 1: frontier list in LDS (16-bit local indices)
     unsigned g;                    // ranges (workgroups) in the gang
     const uint8_t *f1, *f2;        // SoA edge arrays [d][N]
     const uint8_t *A, *B;
     unsigned M;
     unsigned cand_cap;
     void *rec;                     // packed edge records, written by the owners
-    unsigned *lists;               // [g][c] frontier list per range
+    unsigned *lists;               // [g][c] frontier list per range (when not in LDS)
     uint2 *pool;                   // [g][W][S] wheel of each range
     unsigned long long pool_flows;
     uint2 *cand;                   // [2][g][NO][cand_cap] candidates by sender and offset
@@ -991,7 +1006,8 @@ constexpr unsigned CAND_LI = 0x1FFFFu;     // candidate word 0: local index | f1
 constexpr unsigned SF_BAD = 1u << 28;      // an edge with f1 or f2 equal to 0
 
 // Range r of job p, run by the calling workgroup.  smem is the dynamic LDS
-// block: labels | frontier bitmap | B bitmap | wheel fills [MAXW].
+// block: labels | frontier bitmap | B bitmap | wheel fills [MAXW] | frontier
+// list (16-bit local indices, when p.llist).
 //
 // Initialisation (Algorithm 3) packs the range's edge records (per vertex,
 // (f1, f2) of its 2d edges in direction order, zero where the lattice ends),
@@ -1063,6 +1079,8 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     unsigned *bb = fb + cw;
     unsigned *cnt = bb + cw;
     unsigned *mylist = p.lists + (unsigned long long)r * c;
+    const bool llist = p.llist != 0;
+    uint16_t *lds_list = reinterpret_cast<uint16_t *>(smem + lab_words + 2 * cw + MAXW);
     uint2 *const cand = p.cand;
     unsigned *const pubc_base = p.pubc;
     const unsigned long long ccap = p.cand_cap;
@@ -1074,7 +1092,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     };
 
     unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread, committed
-    unsigned long long cC = 0, cP = 0, cI = 0;              // every workgroup alike, from the barrier
+    unsigned long long cC = 0, cP = 0, cI = 0;              // lead workgroup, thread 0, from the barrier
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
     const bool timing = p.prof && lead && tid == 0;
 #define PHASE4(k)                                            \
@@ -1204,7 +1222,8 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 const unsigned bt = (unsigned)(__ffs(bits) - 1);
                 bits &= bits - 1u;
                 const unsigned i = wi * 32u + bt;
-                mylist[k++] = i;
+                if (llist) lds_list[k++] = (uint16_t)i;
+                else mylist[k++] = i;
                 if ((bm >> bt) & 1u) {
                     const unsigned long long key = ((unsigned long long)lget(lab, l16, i) << 32) |
                                                    (0xFFFFFFFFull - (unsigned long long)(base + i));
@@ -1237,7 +1256,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         mine.orf = s_flags & (SF_BAD | SF_INVAL);
         mine.s0 = mine.s1 = mine.s2 = 0;
         mine.mx = s_mf;
-        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all)) status = ST_BROKEN;
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, true)) status = ST_BROKEN;
         else if (all.orf & (SF_BAD | SF_INVAL)) status = ST_INVAL;
         while (W <= (unsigned)all.mx) W <<= 1;
         rr.mf = (unsigned)all.mx;
@@ -1263,11 +1282,26 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         if (tid < NOMAX) s_ccnt[tid] = 0;
         if (tid == 0) s_min = 0xFFFFFFFFu;
         __syncthreads();
+        unsigned amin = 0xFFFFFFFFu;      // least f1 of a shipped candidate
+        // the record of the next frontier vertex is in flight while one is
+        // processed
+        auto front = [&](unsigned j, unsigned &i, RT &rv) {
+            if (j < nlist) {
+                i = llist ? (unsigned)lds_list[j] : mylist[j];
+                rv = rec[base + i];
+            }
+        };
+        unsigned i1 = 0, i2 = 0;
+        RT r1{}, r2{};
+        front(tid, i1, r1);
+        front(tid + BLOCK, i2, r2);
         for (unsigned j = tid; j < nlist; j += BLOCK) {
-            const unsigned i = mylist[j];
-            const long long Q = base + i;
+            const unsigned i = i1;
+            const RT rv = r1;
+            i1 = i2;
+            r1 = r2;
+            front(j + 2 * BLOCK, i2, r2);
             const unsigned L = lget(lab, l16, i);
-            const RT rv = rec[Q];
 #pragma unroll
             for (int dir = 0; dir < 2 * D; ++dir) {
                 unsigned a1, a2;
@@ -1298,10 +1332,12 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                         candbuf(par, r, oi)[pos] = make_uint2(li | (a1 << 17) | (rdir << 25), (unsigned)q);
                     else
                         atomicOr(&s_flags, SF_OVER);
-                    atomicMin(&s_min, a1);
+                    amin = a1 < amin ? a1 : amin;
                 }
             }
         }
+        for (int o = 32; o > 0; o >>= 1) amin = min(amin, (unsigned)__shfl_xor(amin, o));
+        if (lane == 0 && amin != 0xFFFFFFFFu) atomicMin(&s_min, amin);
         __syncthreads();
         // publish candidate fills; next delivery time seen from this range
         if (tid < (unsigned)NO && (int)tid != K) {
@@ -1337,14 +1373,18 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         mine.s1 = nlist;
         mine.s2 = transit;
         mine.mx = s_xkey;
-        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all)) { status = ST_BROKEN; break; }
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false)) { status = ST_BROKEN; break; }
         PHASE4(1);
 
         if (all.orf & SF_OVER) { status = ST_OVERFLOW; break; }
-        if (cyc > 0) {
-            cC += all.s0 > 0 ? 1 : 0;
-            cI = all.s1 > cI ? all.s1 : cI;
-            cP = all.s2 > cP ? all.s2 : cP;
+        if (cyc > 0 && lead && tid == 0) {
+            // the counters' sums are needed by the lead only
+            const unsigned long long a0 = all.rest ? ld64(&all.rest[0]) : all.s0;
+            const unsigned long long a1 = all.rest ? ld64(&all.rest[1]) : all.s1;
+            const unsigned long long a2 = all.rest ? ld64(&all.rest[2]) : all.s2;
+            cC += a0 > 0 ? 1 : 0;
+            cI = a1 > cI ? a1 : cI;
+            cP = a2 > cP ? a2 : cP;
         }
         if (all.orf & SF_BHIT) {
             // ---- Step 6 (Algorithm 2): T = t.  The departure just made is
@@ -1412,11 +1452,23 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         __syncthreads();
         {
             const unsigned FC = s_cpre[NO];
-            for (unsigned j = tid; j < FC; j += BLOCK) {
-                int oi = 0;
-                while (j >= s_cpre[oi + 1]) ++oi;
-                const long long src = (long long)r + (oi - K);
-                const uint2 cd = candbuf(par, (unsigned long long)src, (unsigned)(2 * K - oi))[j - s_cpre[oi]];
+            constexpr int UC = 4;                   // candidate loads in flight per thread
+            for (unsigned j0 = tid; j0 < FC; j0 += BLOCK * UC) {
+              uint2 cdu[UC];
+#pragma unroll
+              for (int u = 0; u < UC; ++u) {
+                const unsigned j = j0 + u * BLOCK;
+                if (j < FC) {
+                    int oi = 0;
+                    while (j >= s_cpre[oi + 1]) ++oi;
+                    const long long src = (long long)r + (oi - K);
+                    cdu[u] = candbuf(par, (unsigned long long)src, (unsigned)(2 * K - oi))[j - s_cpre[oi]];
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < UC; ++u) {
+                if (j0 + u * BLOCK >= FC) continue;
+                const uint2 cd = cdu[u];
                 const unsigned li = cd.x & CAND_LI, a1 = (cd.x >> 17) & 0xFFu, rdir = cd.x >> 25;
                 if (cd.y > lget(lab, l16, li)) {
                     const unsigned bk = (unsigned)((t_prev + a1) & Wm);
@@ -1427,6 +1479,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                         atomicOr(&s_flags, SF_OVER);
                     ++cE;
                 }
+              }
             }
         }
         par ^= 1u;
@@ -1446,10 +1499,21 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             const unsigned bk = (unsigned)(t & Wm);
             F = (unsigned)min((unsigned long long)cnt[bk], S);
             const uint2 *bkt = wheel + (unsigned long long)bk * S;
-            for (unsigned j = tid; j < F; j += BLOCK) {
-                const uint2 f = bkt[j];
-                const unsigned i = (unsigned)((long long)f.x - base);
-                if (lraise(lab, l16, i, f.y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
+            constexpr int UA = 4;                   // flow loads in flight per thread
+            for (unsigned j0 = tid; j0 < F; j0 += BLOCK * UA) {
+                uint2 f[UA];
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const unsigned j = j0 + u * BLOCK;
+                    if (j < F) f[u] = bkt[j];
+                }
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    if (j0 + u * BLOCK < F) {
+                        const unsigned i = (unsigned)((long long)f[u].x - base);
+                        if (lraise(lab, l16, i, f[u].y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
+                    }
+                }
             }
             if (tid == 0) cR += F;
             __syncthreads();
@@ -1738,7 +1802,7 @@ __device__ __forceinline__ void serve_job(const SJ &sj, unsigned r, unsigned *sm
         mine.mn = rr.yd;
         mine.orf = 0;
         mine.s0 = mine.s1 = mine.s2 = mine.mx = 0;
-        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all)) { status = ST_BROKEN; break; }
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false)) { status = ST_BROKEN; break; }
         const unsigned yd = all.mn;
         if (yd >= 2u * D || plen >= sj.path_cap) { status = ST_BROKEN; break; }
         long long oy = 0;
@@ -1957,8 +2021,12 @@ struct LdsPlan {
     long long c = 0;
     int K = 0;
     int lt = 4;
+    int llist = 0;
     size_t lds = 0;
 };
+
+// LDS bytes of a range's frontier list (16-bit local indices)
+size_t lds_list_bytes(long long c) { return (size_t)(((c * 2) + 3) / 4 * 4); }
 
 size_t lds_bytes_for(long long c, int K, int lt)
 {
@@ -2026,6 +2094,10 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
                 pl.K = K;
                 pl.lt = lt;
                 pl.lds = need;
+                if (c <= 65536 && need + lds_list_bytes(c) <= budget) {
+                    pl.llist = 1;
+                    pl.lds = need + lds_list_bytes(c);
+                }
                 return pl;
             }
         }
@@ -2043,6 +2115,7 @@ void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const
     p.d = d;
     p.K = plan.K;
     p.lt = plan.lt;
+    p.llist = plan.llist;
     p.g = (unsigned)plan.G;
     p.f1 = f1;
     p.f2 = f2;
@@ -2057,7 +2130,7 @@ void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const
 // `pool` flows and candidate buffers of `ccap` entries per (sender, offset).
 struct GangPlan {
     long long N = 0, c = 0;
-    int g = 1, K = 0, lt = 4;
+    int g = 1, K = 0, lt = 4, llist = 0;
     size_t lds = 0;
     unsigned long long pool = 0, ccap = 1;
 };
@@ -2084,6 +2157,10 @@ int plan_gang(csp_ctx *ctx, size_t budget, int gmax, int d, long long n, long lo
     pl.K = pl.g == 1 ? 0 : (int)((smax + pl.c - 1) / pl.c);
     if (pl.K > KMAX) return fail(ctx, CSP_EINVAL, "problem ranges too thin");
     pl.lds = lds_bytes_for(pl.c, pl.K, pl.lt);
+    if (pl.c <= 65536 && pl.lds + lds_list_bytes(pl.c) <= budget) {
+        pl.llist = 1;
+        pl.lds += lds_list_bytes(pl.c);
+    }
     pl.pool = ctx->pool_hint ? ctx->pool_hint * 256ull * pl.g : std::max<unsigned long long>(1ull << 15, 6ull * d * N);
     const unsigned long long cmaxc = 2ull * d * (unsigned long long)pl.c;
     pl.ccap = pl.g == 1 ? 1
@@ -2445,7 +2522,7 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
 
     struct Plan {
         long long N, c;
-        int g, K, lt;
+        int g, K, lt, llist;
         size_t lds;
         unsigned long long pool, ccap;
         size_t off_rec, off_lists, off_pool, off_cand, off_pubc, off_bar, off_out, end;
@@ -2476,6 +2553,7 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
         pl.g = gp.g;
         pl.K = gp.K;
         pl.lt = gp.lt;
+        pl.llist = gp.llist;
         pl.lds = gp.lds;
         pl.pool = gp.pool;
         pl.ccap = gp.ccap;
@@ -2547,6 +2625,7 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
             lp.c = pl.c;
             lp.K = pl.K;
             lp.lt = pl.lt;
+            lp.llist = pl.llist;
             lp.lds = pl.lds;
             RJ &p = hjobs[j];
             fill_job(p, q.d, q.n, pl.N, lp, q.f1, q.f2, q.A, q.B, q.M);
@@ -2848,6 +2927,7 @@ int srv_admit(csp_server *s)
         lp.c = r.plan.c;
         lp.K = r.plan.K;
         lp.lt = r.plan.lt;
+        lp.llist = r.plan.llist;
         lp.lds = r.plan.lds;
         fill_job(w.rj, r.q.d, r.q.n, r.N, lp, r.q.f1, r.q.f2, r.q.A, r.q.B, r.q.M);
         auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };

@@ -22,7 +22,7 @@ COPY_BYTES = 1 << 30
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="cube128",
-                    choices=["cube128", "cube256", "cube256stress", "square64"])
+                    choices=["cube128", "cube128set", "cube256", "cube256stress", "square64"])
     ap.add_argument("--M", type=int, default=700)
     ap.add_argument("--solves", type=int, default=3)
     args = ap.parse_args()
@@ -39,14 +39,18 @@ def main():
     print(f"copy {COPY_BYTES} bytes done", flush=True)
     del a, b
 
-    inst = {"cube128": lambda: gen.cube128(11, args.M), "cube256": lambda: gen.cube256(21),
-            "cube256stress": lambda: gen.cube256_stress(22), "square64": lambda: gen.square64(1)}[args.workload]()
-    di = csp.to_device(inst)
+    insts = {"cube128": lambda: [gen.cube128(11, args.M)],
+             "cube128set": lambda: [gen.cube128(11, M) for M in (400, 700, 1000)],
+             "cube256": lambda: [gen.cube256(21)],
+             "cube256stress": lambda: [gen.cube256_stress(22)],
+             "square64": lambda: [gen.square64(1)]}[args.workload]()
     s = csp.Solver(0)
-    for i in range(args.solves):
-        res, cnt = s.solve(di)
-        print(f"solve {i}: {res.tuple()} C={cnt.C} R={cnt.R} kernel_ms={csp.csp_last_kernel_ms(s.ctx):.3f}",
-              flush=True)
+    for inst in insts:
+        di = csp.to_device(inst)
+        for i in range(args.solves):
+            res, cnt = s.solve(di)
+            print(f"{inst.name} solve {i}: {res.tuple()} C={cnt.C} R={cnt.R} "
+                  f"kernel_ms={csp.csp_last_kernel_ms(s.ctx):.3f}", flush=True)
     s.close()
 
 
