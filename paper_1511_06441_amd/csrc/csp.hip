@@ -1050,6 +1050,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     __shared__ unsigned long long s_sum;
     __shared__ unsigned long long s_red[4];
     __shared__ unsigned s_ccnt[NOMAX];        // candidates shipped / received this cycle
+    __shared__ unsigned s_nl, s_bhn;          // size of I_t; improved vertices of B
     __shared__ unsigned s_cpre[NOMAX + 1];
 
     const unsigned tid = threadIdx.x, lane = lane_id();
@@ -1301,6 +1302,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             i1 = i2;
             r1 = r2;
             front(j + 2 * BLOCK, i2, r2);
+            fb[i >> 5] = 0;                 // every vertex of the word is in this list
             const unsigned L = lget(lab, l16, i);
 #pragma unroll
             for (int dir = 0; dir < 2 * D; ++dir) {
@@ -1311,8 +1313,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 const int q = (int)L - (int)a2;
                 if (q <= 0) continue;
                 const long long lo = (long long)i + offr[dir];
-                const int o = (int)offq[dir] + (lo >= c ? 1 : 0);
-                const unsigned li = (unsigned)(lo >= c ? lo - c : lo);   // index in the owner's range
+                const bool wrap = lo >= c;
+                const int o = (int)offq[dir] + (wrap ? 1 : 0);
+                const unsigned li = (unsigned)(wrap ? lo - c : lo);     // index in the owner's range
                 const unsigned rdir = (unsigned)(2 * D - 1 - dir);      // sender seen from the receiver
                 if (o == 0) {
                     if ((unsigned)q > lget(lab, l16, li)) {
@@ -1327,7 +1330,15 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                     }
                 } else {
                     const unsigned oi = (unsigned)(o + K);
-                    const unsigned pos = atomicAdd(&s_ccnt[oi], 1u);
+                    // for one direction a wave ships to at most two receivers:
+                    // the lanes of each share one LDS atomic
+                    const unsigned long long mw = __ballot(wrap), ma = __ballot(1);
+                    const unsigned long long grp = wrap ? mw : (ma & ~mw);
+                    const int leader = __ffsll((long long)grp) - 1;
+                    unsigned first = 0;
+                    if ((int)lane == leader) first = atomicAdd(&s_ccnt[oi], (unsigned)__popcll(grp));
+                    first = __shfl(first, leader);
+                    const unsigned pos = first + (unsigned)__popcll(grp & ((1ull << lane) - 1ull));
                     if (pos < CS)
                         candbuf(par, r, oi)[pos] = make_uint2(li | (a1 << 17) | (rdir << 25), (unsigned)q);
                     else
@@ -1483,7 +1494,13 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             }
         }
         par ^= 1u;
-        if (tid == 0) s_sum = 0;
+        if (tid == 0) {
+            s_sum = 0;
+            s_nl = 0;
+            s_bhn = 0;
+            s_flags &= SF_OVER;
+            s_xkey = 0;
+        }
         __syncthreads();
         PHASE4(2);
         // flows in transit after the sending round at t_prev
@@ -1511,24 +1528,55 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 for (int u = 0; u < UA; ++u) {
                     if (j0 + u * BLOCK < F) {
                         const unsigned i = (unsigned)((long long)f[u].x - base);
-                        if (lraise(lab, l16, i, f[u].y >> 3)) atomicOr(&fb[i >> 5], 1u << (i & 31));
+                        if (lraise(lab, l16, i, f[u].y >> 3)) {
+                            // the first raise of a vertex this cycle puts it in I_t
+                            const unsigned bit = 1u << (i & 31);
+                            if (!(atomicOr(&fb[i >> 5], bit) & bit)) {
+                                const unsigned long long am = __ballot(1);
+                                const int ld = __ffsll((long long)am) - 1;
+                                unsigned k0 = 0;
+                                if ((int)lane == ld) k0 = atomicAdd(&s_nl, (unsigned)__popcll(am));
+                                const unsigned k = __shfl(k0, ld) + (unsigned)__popcll(am & ((1ull << lane) - 1ull));
+                                if (llist) lds_list[k] = (uint16_t)i;
+                                else mylist[k] = i;
+                                if (bb[i >> 5] & bit) atomicAdd(&s_bhn, 1u);
+                            }
+                        }
                     }
                 }
             }
             if (tid == 0) cR += F;
             __syncthreads();
+            nlist = s_nl;
+            if (s_bhn) {
+                // a vertex of B improved: best (label, -index) over them, with
+                // the labels after every delivery of this cycle
+                unsigned long long bestB = 0;
+                for (unsigned j = tid; j < nlist; j += BLOCK) {
+                    const unsigned i = llist ? (unsigned)lds_list[j] : mylist[j];
+                    if (bb[i >> 5] & (1u << (i & 31))) {
+                        const unsigned long long key = ((unsigned long long)lget(lab, l16, i) << 32) |
+                                                       (0xFFFFFFFFull - (unsigned long long)(base + i));
+                        bestB = key > bestB ? key : bestB;
+                    }
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    const unsigned long long ob = __shfl_xor(bestB, o);
+                    bestB = ob > bestB ? ob : bestB;
+                }
+                if (lane == 0 && bestB) {
+                    atomicMax(&s_xkey, bestB);
+                    atomicOr(&s_flags, SF_BHIT);
+                }
+            }
             if (tid == 0) {
                 cnt[bk] = 0;
-                s_flags &= SF_OVER;
-                s_xkey = 0;
+                cU += nlist;
             }
             __syncthreads();
             transit = s_sum;
         }
         PHASE4(3);
-        nlist = compact();
-        if (tid == 0) cU += nlist;
-        PHASE4(4);
     }
 #undef PHASE4
 
