@@ -152,9 +152,11 @@ int csp_set_pool_hint(csp_ctx *ctx, uint64_t flows_per_bucket);
 int csp_set_blocks(csp_ctx *ctx, int blocks);
 
 /* Kernel choice for later solves on ctx: 0 = automatic, 1 = range-owned
- * (each workgroup keeps its range's labels in LDS; CSP_EINVAL when a range
- * cannot fit), 2 = global labels.  Changes speed, never results.
- * csp_last_path returns the kernel (1 or 2) the last solve used. */
+ * (each workgroup keeps a range of consecutive vertex indices, with their
+ * labels in LDS; CSP_EINVAL when a range cannot fit), 2 = global labels,
+ * 3 = range-owned with x-pencil ranges for d = 3 (n x t x t vertices; other
+ * d as 1).  Changes speed, never results.  csp_last_path returns the kernel
+ * (1 range-owned, 2 global labels) the last solve used. */
 int csp_set_path(csp_ctx *ctx, int path);
 int csp_last_path(const csp_ctx *ctx);
 

@@ -941,7 +941,10 @@ struct RJ {
     int d;
     int K;                         // neighbours lie within K ranges
     int lt;                        // LDS label bytes (2 or 4)
-    int llist;                     // 1: frontier list in LDS (16-bit local indices)
+    int llist;                     // frontier list entries kept in LDS (16-bit local indices); the rest in lists
+    int tile;                      // 1 (d = 3): ranges are x-pencils of n x ty x tz vertices
+    int ty, tz;                    // pencil extent along y and z
+    unsigned nty;                  // pencils along y
     unsigned g;                    // ranges (workgroups) in the gang
     const uint8_t *f1, *f2;        // SoA edge arrays [d][N]
     const uint8_t *A, *B;
@@ -962,6 +965,10 @@ struct RJ {
 };
 
 template <typename LT> __device__ __forceinline__ unsigned lab_get(const LT *lab, unsigned i) { return lab[i]; }
+
+// pencil-face flags kept in the spare word of a 3-d record
+template <typename RT> __device__ __forceinline__ unsigned rec_cross(const RT &) { return 0; }
+template <> __device__ __forceinline__ unsigned rec_cross<uint4>(const uint4 &v) { return v.w; }
 
 // raise lab[i] to q; true when this call raised it
 __device__ __forceinline__ bool lab_raise(unsigned *lab, unsigned i, unsigned q)
@@ -1007,7 +1014,7 @@ constexpr unsigned SF_BAD = 1u << 28;      // an edge with f1 or f2 equal to 0
 
 // Range r of job p, run by the calling workgroup.  smem is the dynamic LDS
 // block: labels | frontier bitmap | B bitmap | wheel fills [MAXW] | frontier
-// list (16-bit local indices, when p.llist).
+// list (the first p.llist entries, 16-bit local indices).
 //
 // Initialisation (Algorithm 3) packs the range's edge records (per vertex,
 // (f1, f2) of its 2d edges in direction order, zero where the lattice ends),
@@ -1036,7 +1043,7 @@ struct RunRes {
 // initialisation (reinit_mf == 0) writes it; a later solve of the same
 // lattice passes the largest f1 seen before as reinit_mf and starts from
 // abits, without re-reading or re-packing the edges.
-template <int D>
+template <int D, bool TILE = false>
 __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M, long long bvert, unsigned &epoch,
                             Out *out, unsigned *abits = nullptr, unsigned reinit_mf = 0)
 {
@@ -1068,8 +1075,36 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         offr[dir] = o - q * c;
     }
     const long long base = (long long)r * c;
-    const unsigned cr = (unsigned)max(0ll, min(c, N - base));
-    const int K = p.K, NO = 2 * K + 1;
+    // Pencil ranges (d = 3): range r holds x = 0..n-1, y in [ry ty, ry ty + ty),
+    // z in [rz tz, rz tz + tz), local index x + n (ly + ty lz); a range at the
+    // far faces can be partial.  Contiguous ranges hold vertices base..base+c-1.
+    constexpr bool tile = D == 3 && TILE;
+    const long long ty = p.ty, tz = p.tz;
+    const long long ry = tile ? (long long)(r % p.nty) : 0, rz = tile ? (long long)(r / p.nty) : 0;
+    const unsigned cr = tile ? (unsigned)c : (unsigned)max(0ll, min(c, N - base));
+    const int K = p.K, NO = tile ? 2 * D : 2 * K + 1;
+    // global index of local vertex i (-1 outside the lattice)
+    auto gvert = [=](unsigned i) -> long long {
+        if (!tile) return base + i;
+        const long long x = i % n, q = i / n, y = ry * ty + q % ty, z = rz * tz + q / ty;
+        return (y < n && z < n) ? x + n * (y + n * z) : -1;
+    };
+    // range and local index of global vertex v
+    auto locate = [=](long long v, long long &li) -> long long {
+        if (!tile) {
+            li = v % c;
+            return v / c;
+        }
+        const long long x = v % n, y = (v / n) % n, z = v / (n * n);
+        const long long qy = y / ty, qz = z / tz;
+        li = x + n * ((y - qy * ty) + ty * (z - qz * tz));
+        return qy + (long long)p.nty * qz;
+    };
+    // target range offset of candidate slot s (a receiver reads slot s from range r - soff(s))
+    auto soff = [=](int sl) -> long long {
+        if (!tile) return (long long)(sl - K);
+        return sl == 0 ? -(long long)p.nty : sl == 1 ? -1 : sl == 2 * D - 2 ? 1 : sl == 2 * D - 1 ? (long long)p.nty : 0;
+    };
     RT *rec = static_cast<RT *>(p.rec);
 
     const unsigned cw = (unsigned)((c + 31) / 32);
@@ -1080,8 +1115,13 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     unsigned *bb = fb + cw;
     unsigned *cnt = bb + cw;
     unsigned *mylist = p.lists + (unsigned long long)r * c;
-    const bool llist = p.llist != 0;
     uint16_t *lds_list = reinterpret_cast<uint16_t *>(smem + lab_words + 2 * cw + MAXW);
+    const unsigned lcap = (unsigned)p.llist;
+    auto list_put = [=](unsigned k, unsigned i) {
+        if (k < lcap) lds_list[k] = (uint16_t)i;
+        else mylist[k] = i;
+    };
+    auto list_get = [=](unsigned k) -> unsigned { return k < lcap ? (unsigned)lds_list[k] : mylist[k]; };
     uint2 *const cand = p.cand;
     unsigned *const pubc_base = p.pubc;
     const unsigned long long ccap = p.cand_cap;
@@ -1129,8 +1169,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         }
         if (tid == 0) {
             s_mf = reinit_mf;
-            if (bvert >= base && bvert < base + (long long)cr) {
-                const unsigned i = (unsigned)(bvert - base);
+            long long bl = 0;
+            if (bvert >= 0 && locate(bvert, bl) == (long long)r) {
+                const unsigned i = (unsigned)bl;
                 bb[i >> 5] |= 1u << (i & 31);
             }
         }
@@ -1145,7 +1186,11 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             }
         }
         for (unsigned i = tid; i < cr; i += BLOCK) {
-            const long long v = base + i;
+            const long long v = gvert(i);
+            if (v < 0) {
+                rec[base + i] = RT{};       // outside the lattice: no edges
+                continue;
+            }
             long long cc[D];
             long long rem = v;
 #pragma unroll
@@ -1174,12 +1219,19 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             } else if constexpr (D == 2) {
                 rv = make_uint2(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16));
             } else if constexpr (D == 3) {
-                rv = make_uint4(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16), pr[4] | (pr[5] << 16), 0u);
+                // word 3: directions whose neighbour lies in another pencil
+                unsigned cross = 0;
+                if (tile) {
+                    const long long q = (long long)i / n, ly = q % ty, lz = q / ty;
+                    cross = (lz == 0 ? 1u : 0u) | (ly == 0 ? 2u : 0u) | (ly == ty - 1 ? 16u : 0u) |
+                            (lz == tz - 1 ? 32u : 0u);
+                }
+                rv = make_uint4(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16), pr[4] | (pr[5] << 16), cross);
             } else {
                 rv = make_uint4(pr[0] | (pr[1] << 16), pr[2] | (pr[3] << 16), pr[4] | (pr[5] << 16),
                                 pr[6] | (pr[7] << 16));
             }
-            rec[v] = rv;
+            rec[base + i] = rv;
             const bool a = p.A[v] != 0, b = bvert >= 0 ? v == bvert : p.B[v] != 0;
             if (a && b) bad |= 2;
             if (a) {
@@ -1223,11 +1275,10 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 const unsigned bt = (unsigned)(__ffs(bits) - 1);
                 bits &= bits - 1u;
                 const unsigned i = wi * 32u + bt;
-                if (llist) lds_list[k++] = (uint16_t)i;
-                else mylist[k++] = i;
+                list_put(k++, i);
                 if ((bm >> bt) & 1u) {
                     const unsigned long long key = ((unsigned long long)lget(lab, l16, i) << 32) |
-                                                   (0xFFFFFFFFull - (unsigned long long)(base + i));
+                                                   (0xFFFFFFFFull - (unsigned long long)gvert(i));
                     bestB = key > bestB ? key : bestB;
                 }
             }
@@ -1288,7 +1339,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         // processed
         auto front = [&](unsigned j, unsigned &i, RT &rv) {
             if (j < nlist) {
-                i = llist ? (unsigned)lds_list[j] : mylist[j];
+                i = list_get(j);
                 rv = rec[base + i];
             }
         };
@@ -1312,10 +1363,29 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 ++dD;
                 const int q = (int)L - (int)a2;
                 if (q <= 0) continue;
-                const long long lo = (long long)i + offr[dir];
-                const bool wrap = lo >= c;
-                const int o = (int)offq[dir] + (wrap ? 1 : 0);
-                const unsigned li = (unsigned)(wrap ? lo - c : lo);     // index in the owner's range
+                bool wrap;
+                int o;
+                unsigned li;                                            // index in the owner's range
+                if (tile) {
+                    // within the pencil, or across its y / z face
+                    long long lstep = 1, span = 1;
+                    if (dir == 0 || dir == 2 * D - 1) { lstep = n * ty; span = tz; }
+                    if (dir == 1 || dir == 2 * D - 2) { lstep = n; span = ty; }
+                    const bool up = dir >= D;
+                    wrap = false;
+                    if (rec_cross(rv) & (1u << dir)) {
+                        o = 1;                                          // any nonzero: candidate slot dir
+                        li = (unsigned)((long long)i + (up ? -(span - 1) : (span - 1)) * lstep);
+                    } else {
+                        o = 0;
+                        li = (unsigned)((long long)i + (up ? lstep : -lstep));
+                    }
+                } else {
+                    const long long lo = (long long)i + offr[dir];
+                    wrap = lo >= c;
+                    o = (int)offq[dir] + (wrap ? 1 : 0);
+                    li = (unsigned)(wrap ? lo - c : lo);
+                }
                 const unsigned rdir = (unsigned)(2 * D - 1 - dir);      // sender seen from the receiver
                 if (o == 0) {
                     if ((unsigned)q > lget(lab, l16, li)) {
@@ -1329,7 +1399,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                         ++dE;
                     }
                 } else {
-                    const unsigned oi = (unsigned)(o + K);
+                    const unsigned oi = tile ? (unsigned)dir : (unsigned)(o + K);
                     // for one direction a wave ships to at most two receivers:
                     // the lanes of each share one LDS atomic
                     const unsigned long long mw = __ballot(wrap), ma = __ballot(1);
@@ -1351,7 +1421,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         if (lane == 0 && amin != 0xFFFFFFFFu) atomicMin(&s_min, amin);
         __syncthreads();
         // publish candidate fills; next delivery time seen from this range
-        if (tid < (unsigned)NO && (int)tid != K) {
+        if (tid < (unsigned)NO && soff((int)tid) != 0) {
             const unsigned v = s_ccnt[tid];
             if (v > CS) atomicOr(&s_flags, SF_OVER);
             __hip_atomic_store(pubc(par, r, tid), min(v, CS), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1404,11 +1474,13 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             found = true;
             const unsigned X = (unsigned)(0xFFFFFFFFull - (all.mx & 0xFFFFFFFFull));
             const unsigned LX = (unsigned)(all.mx >> 32);
-            if ((long long)X >= base && (long long)X < base + (long long)cr) {
+            long long xl = 0;
+            if (locate((long long)X, xl) == (long long)r) {
+                const unsigned Xr = (unsigned)(base + xl);              // X as a wheel entry names it
                 const uint2 *bkt = wheel + (unsigned long long)(t & Wm) * S;
                 for (unsigned j = tid; j < F; j += BLOCK) {
                     const uint2 f = bkt[j];
-                    if (f.x == X && (f.y >> 3) == LX) atomicMin(&s_ydir, f.y & 7u);
+                    if (f.x == Xr && (f.y >> 3) == LX) atomicMin(&s_ydir, f.y & 7u);
                 }
                 __syncthreads();
                 if (tid == 0) {
@@ -1447,11 +1519,11 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         // ---- Steps 4-5 across ranges: test candidates shipped at t_prev
         // against this range's labels (still L_{t_prev}) and file the flows.
         if (tid < (unsigned)NO) {
-            const int dd = (int)tid - K;                 // sender range r + dd
-            const long long src = (long long)r + dd;
+            const long long so = soff((int)tid);         // slot tid comes from range r - so
+            const long long src = (long long)r - so;
             unsigned v = 0;
-            if (dd != 0 && src >= 0 && src < (long long)G)
-                v = __hip_atomic_load(pubc(par, (unsigned long long)src, (unsigned)(K - dd)), __ATOMIC_RELAXED,
+            if (so != 0 && src >= 0 && src < (long long)G)
+                v = __hip_atomic_load(pubc(par, (unsigned long long)src, tid), __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
             s_ccnt[tid] = v;
         }
@@ -1472,8 +1544,8 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 if (j < FC) {
                     int oi = 0;
                     while (j >= s_cpre[oi + 1]) ++oi;
-                    const long long src = (long long)r + (oi - K);
-                    cdu[u] = candbuf(par, (unsigned long long)src, (unsigned)(2 * K - oi))[j - s_cpre[oi]];
+                    const long long src = (long long)r - soff(oi);
+                    cdu[u] = candbuf(par, (unsigned long long)src, (unsigned)oi)[j - s_cpre[oi]];
                 }
               }
 #pragma unroll
@@ -1537,8 +1609,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                                 unsigned k0 = 0;
                                 if ((int)lane == ld) k0 = atomicAdd(&s_nl, (unsigned)__popcll(am));
                                 const unsigned k = __shfl(k0, ld) + (unsigned)__popcll(am & ((1ull << lane) - 1ull));
-                                if (llist) lds_list[k] = (uint16_t)i;
-                                else mylist[k] = i;
+                                list_put(k, i);
                                 if (bb[i >> 5] & bit) atomicAdd(&s_bhn, 1u);
                             }
                         }
@@ -1553,10 +1624,10 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 // the labels after every delivery of this cycle
                 unsigned long long bestB = 0;
                 for (unsigned j = tid; j < nlist; j += BLOCK) {
-                    const unsigned i = llist ? (unsigned)lds_list[j] : mylist[j];
+                    const unsigned i = list_get(j);
                     if (bb[i >> 5] & (1u << (i & 31))) {
                         const unsigned long long key = ((unsigned long long)lget(lab, l16, i) << 32) |
-                                                       (0xFFFFFFFFull - (unsigned long long)(base + i));
+                                                       (0xFFFFFFFFull - (unsigned long long)gvert(i));
                         bestB = key > bestB ? key : bestB;
                     }
                 }
@@ -1582,7 +1653,10 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
 
     // ---- outputs
     if (status == ST_DONE && p.labels_out) {
-        for (unsigned i = tid; i < cr; i += BLOCK) p.labels_out[base + i] = lget(lab, l16, i);
+        for (unsigned i = tid; i < cr; i += BLOCK) {
+            const long long v = gvert(i);
+            if (v >= 0) p.labels_out[v] = lget(lab, l16, i);
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -1622,14 +1696,14 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
 
 // Single solve: the whole grid is one gang; range r of physical block b is
 // chosen so that each XCD (blocks b = x mod 8) holds a contiguous run.
-template <int D>
+template <int D, bool TILE = false>
 __global__ void __launch_bounds__(BLOCK) k_ranges(RJ p)
 {
     extern __shared__ unsigned smem[];
     const unsigned G = gridDim.x;
     const unsigned r = (G % NGRP) == 0 ? (blockIdx.x % NGRP) * (G / NGRP) + blockIdx.x / NGRP : blockIdx.x;
     unsigned epoch = 0;
-    (void)range_run<D>(p, r, smem, p.M, -1, epoch, p.out);
+    (void)range_run<D, TILE>(p, r, smem, p.M, -1, epoch, p.out);
 }
 
 // Batched solves in one persistent launch.  Work is a list of (job, range)
@@ -2040,13 +2114,12 @@ int grow(csp_ctx *ctx, T **p, size_t &cap, size_t need, const char *what)
     return CSP_OK;
 }
 
-const void *lds_kernel(int d, int lt)
+const void *lds_kernel(int d, int tile)
 {
-    (void)lt;
     switch (d) {
     case 1: return (const void *)k_ranges<1>;
     case 2: return (const void *)k_ranges<2>;
-    case 3: return (const void *)k_ranges<3>;
+    case 3: return tile ? (const void *)k_ranges<3, true> : (const void *)k_ranges<3>;
     default: return (const void *)k_ranges<4>;
     }
 }
@@ -2070,11 +2143,23 @@ struct LdsPlan {
     int K = 0;
     int lt = 4;
     int llist = 0;
+    int tile = 0;                   // d = 3: x-pencils of n x ty x tz
+    int ty = 0, tz = 0, nty = 0;
     size_t lds = 0;
 };
 
 // LDS bytes of a range's frontier list (16-bit local indices)
 size_t lds_list_bytes(long long c) { return (size_t)(((c * 2) + 3) / 4 * 4); }
+
+// Frontier-list entries a range of c vertices keeps in LDS beside `need`
+// bytes (the list is usually far shorter than the range); 16-bit local
+// indices need c <= 65536.
+long long lds_list_cap(long long c, size_t need, size_t budget)
+{
+    if (c > 65536 || need >= budget) return 0;
+    const long long room = (long long)((budget - need) / 4) * 2;
+    return std::min(c, room);
+}
 
 size_t lds_bytes_for(long long c, int K, int lt)
 {
@@ -2127,6 +2212,40 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
     long long smax = 1;
     for (int k = 1; k < d; ++k) smax *= n;           // largest neighbour offset
     const size_t budget = ctx->lds_limit > 4096 ? ctx->lds_limit - 4096 : 0;   // static LDS margin
+    // 3-d lattices on request: x-pencils (every range spans x, so a front
+    // moving along x is shared by all ranges, and only the y and z faces of a
+    // pencil ship candidates), m x m pencils with m^2 close to G_want.  They
+    // ship about a quarter of the candidates of whole-plane ranges but
+    // measured slower on MI355X (more spread in per-range departure work),
+    // so consecutive-index ranges are the default.
+    if (d == 3 && G_want >= 4 && ctx->path_override == 3) {
+        int m = 1;
+        while ((m + 1) * (m + 1) <= G_want) ++m;
+        for (; m >= 2; --m) {
+            const long long t = (n + m - 1) / m, mm = (n + t - 1) / t;
+            const long long c = n * t * t;
+            bool done = false;
+            for (int lt : {4, 2}) {
+                if (lt == 2 && M > 0xFFFFu) continue;
+                const size_t need = lds_bytes_for(c, 0, lt);
+                if (c <= 0x1FFFF && need <= budget) {
+                    pl.ok = true;
+                    pl.G = (int)(mm * mm);
+                    pl.c = c;
+                    pl.K = 0;
+                    pl.lt = lt;
+                    pl.tile = 1;
+                    pl.ty = pl.tz = (int)t;
+                    pl.nty = (int)mm;
+                    pl.llist = (int)lds_list_cap(c, need, budget);
+                    pl.lds = need + lds_list_bytes(pl.llist);
+                    done = true;
+                    break;
+                }
+            }
+            if (done) return pl;
+        }
+    }
     for (int G = std::max(1, G_want); G >= 1; G = (G > 1 ? G / 2 : 0)) {
         const long long c = (N + G - 1) / G;
         if ((long long)(G - 1) * c >= N) continue;    // empty range
@@ -2141,11 +2260,8 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
                 pl.c = c;
                 pl.K = K;
                 pl.lt = lt;
-                pl.lds = need;
-                if (c <= 65536 && need + lds_list_bytes(c) <= budget) {
-                    pl.llist = 1;
-                    pl.lds = need + lds_list_bytes(c);
-                }
+                pl.llist = (int)lds_list_cap(c, need, budget);
+                pl.lds = need + lds_list_bytes(pl.llist);
                 return pl;
             }
         }
@@ -2164,6 +2280,10 @@ void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const
     p.K = plan.K;
     p.lt = plan.lt;
     p.llist = plan.llist;
+    p.tile = plan.tile;
+    p.ty = plan.ty;
+    p.tz = plan.tz;
+    p.nty = (unsigned)plan.nty;
     p.g = (unsigned)plan.G;
     p.f1 = f1;
     p.f2 = f2;
@@ -2183,7 +2303,8 @@ struct GangPlan {
     unsigned long long pool = 0, ccap = 1;
 };
 
-int plan_gang(csp_ctx *ctx, size_t budget, int gmax, int d, long long n, long long N, uint32_t M, GangPlan &pl)
+int plan_gang(csp_ctx *ctx, size_t budget, int gmax, int d, long long n, long long N, uint32_t M, GangPlan &pl,
+              int g_want = 0)
 {
     pl.N = N;
     pl.lt = M <= 0xFFFFu ? 2 : 4;
@@ -2197,18 +2318,26 @@ int plan_gang(csp_ctx *ctx, size_t budget, int gmax, int d, long long n, long lo
         }
         cmax = lo;
     }
-    pl.g = (int)std::min<long long>((N + cmax - 1) / cmax, std::min(gmax, GMAX));
-    pl.c = (N + pl.g - 1) / pl.g;
-    if (pl.c > cmax) return fail(ctx, CSP_EINVAL, "problem too large for one launch");
+    // the fewest workgroups whose ranges fit LDS, or more when asked (shorter
+    // cycles for a lone problem) while neighbours stay within KMAX ranges
+    const long long gcap = std::min(gmax, GMAX);
+    const long long gmin = std::min<long long>((N + cmax - 1) / cmax, gcap);
     long long smax = 1;
     for (int k = 1; k < d; ++k) smax *= n;
+    long long g = std::max<long long>(gmin, std::min<long long>(g_want, gcap));
+    while (g > gmin) {
+        const long long c = (N + g - 1) / g;
+        if ((g - 1) * c < N && (smax + c - 1) / c <= KMAX) break;
+        --g;
+    }
+    pl.g = (int)g;
+    pl.c = (N + pl.g - 1) / pl.g;
+    if (pl.c > cmax) return fail(ctx, CSP_EINVAL, "problem too large for one launch");
     pl.K = pl.g == 1 ? 0 : (int)((smax + pl.c - 1) / pl.c);
     if (pl.K > KMAX) return fail(ctx, CSP_EINVAL, "problem ranges too thin");
     pl.lds = lds_bytes_for(pl.c, pl.K, pl.lt);
-    if (pl.c <= 65536 && pl.lds + lds_list_bytes(pl.c) <= budget) {
-        pl.llist = 1;
-        pl.lds += lds_list_bytes(pl.c);
-    }
+    pl.llist = (int)lds_list_cap(pl.c, pl.lds, budget);
+    pl.lds += lds_list_bytes(pl.llist);
     pl.pool = ctx->pool_hint ? ctx->pool_hint * 256ull * pl.g : std::max<unsigned long long>(1ull << 15, 6ull * d * N);
     const unsigned long long cmaxc = 2ull * d * (unsigned long long)pl.c;
     pl.ccap = pl.g == 1 ? 1
@@ -2321,7 +2450,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     if (ctx->path_override != 2) {
         plan = plan_lds(ctx, d, n, N, M, G);
         if (plan.ok) {
-            const void *kf = lds_kernel(d, plan.lt);
+            const void *kf = lds_kernel(d, plan.tile);
             if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds) != hipSuccess)
                 plan.ok = false;
             int nb = 0;
@@ -2329,7 +2458,8 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
                             nb * ctx->num_cu < plan.G))
                 plan.ok = false;
         }
-        if (!plan.ok && ctx->path_override == 1) return fail(ctx, CSP_EINVAL, "range does not fit in LDS");
+        if (!plan.ok && (ctx->path_override == 1 || ctx->path_override == 3))
+            return fail(ctx, CSP_EINVAL, "range does not fit in LDS");
     }
     const bool use_lds = plan.ok;
     if (use_lds) G = plan.G;
@@ -2338,7 +2468,11 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     // wheel capacity: start from the largest a solve has needed, at least
     // 16 flows per directed-edge endpoint; doubled on overflow up to the
     // bound at which no bucket can overflow
-    const unsigned long long NO = use_lds ? (unsigned long long)(2 * plan.K + 1) : 1ull;
+    const unsigned long long NO = use_lds ? (unsigned long long)(plan.tile ? 2 * d : 2 * plan.K + 1) : 1ull;
+    if (use_lds) {
+        rc = grow(ctx, &ctx->rec, ctx->rec_cap, (size_t)(plan.c * G) * rec_bytes(d), "edge records");
+        if (rc) return rc;
+    }
     unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G
                                              : std::max<unsigned long long>(
                                                    std::max<unsigned long long>(1ull << 20, 16ull * d * N),
@@ -2352,6 +2486,8 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
                                                           {4096ull, (unsigned long long)plan.c / 2, ctx->cand_seen}))
                                       : 0ull;
     if (use_lds && ctx->pool_hint) ccap = std::min<unsigned long long>(cand_max, 64ull);
+    // a pencil face of n t vertices ships at most one candidate per vertex and cycle
+    if (use_lds && plan.tile && !ctx->pool_hint) ccap = (unsigned long long)n * plan.ty;
 
     for (;;) {
         rc = grow(ctx, &ctx->pool, ctx->pool_cap, (size_t)pool, "transit pool");
@@ -2381,7 +2517,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             p.prof = ctx->prof;
             void *args[] = {&p};
             HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
-            HIP_TRY(hipLaunchCooperativeKernel(lds_kernel(d, plan.lt), dim3(G), dim3(BLOCK), args,
+            HIP_TRY(hipLaunchCooperativeKernel(lds_kernel(d, plan.tile), dim3(G), dim3(BLOCK), args,
                                                (unsigned)plan.lds, s),
                     "solve launch");
             HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
@@ -3198,7 +3334,10 @@ int csp_serve_submit(csp_server *s, const csp_request *req)
     r.q.reconstruct = q.reconstruct ? 1 : 0;
     int rc = check_shape(ctx, q.d, q.n, q.M, r.N);
     if (rc) return rc;
-    rc = plan_gang(ctx, s->lds, s->workers, q.d, q.n, r.N, q.M, r.plan);
+    // a served request gets about one workgroup per 8K vertices (up to half
+    // the workers): its reconstruction chain is a long run of short cycles
+    const int g_want = (int)std::min<long long>((r.N + 8191) / 8192, std::max(1, s->workers / 2));
+    rc = plan_gang(ctx, s->lds, s->workers, q.d, q.n, r.N, q.M, r.plan, r.N <= 32768 ? 1 : g_want);
     if (rc) return rc;
     if (srv_footprint(r) > s->dev_alloc.cap) return fail(ctx, CSP_ENOMEM, "request larger than the serving arena");
     if (srv_path_words(r) * 8 > s->path_alloc.cap) return fail(ctx, CSP_ENOMEM, "path longer than the path pool");
@@ -3283,7 +3422,7 @@ int csp_serve_close(csp_server *s)
 
 int csp_set_path(csp_ctx *ctx, int path)
 {
-    if (!ctx || path < 0 || path > 2) return CSP_EINVAL;
+    if (!ctx || path < 0 || path > 3) return CSP_EINVAL;
     ctx->path_override = path;
     return CSP_OK;
 }
