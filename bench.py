@@ -208,6 +208,25 @@ def algorithmic_bytes(N, c):
             + c["R"] * (FLOW_BYTES + 2 * L))
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, when it was taken on the current kernel source; else None."""
+    import hashlib
+    import re
+    summary = os.path.join(ROOT, "profiles", f"k_ranges3_{workload}_traffic.md")
+    src = os.path.join(ROOT, "paper_1511_06441_amd", "csrc", "csp.hip")
+    if not os.path.exists(summary):
+        return None
+    text = open(summary).read()
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_h = re.search(r"csp_hip_sha256:\s*([0-9a-f]{64})", text)
+    if not (m_b and m_h):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
+        return None
+    return float(m_b.group(1))
+
+
 def cpu_baseline(inst):
     from oracle import oracle as O
     t0 = time.perf_counter()
@@ -303,7 +322,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
             "kernel_ms_avg": sum(kern_ms) / len(kern_ms),
             "algorithmic_bytes_per_step": bytes_step,
         },
