@@ -160,6 +160,18 @@ int csp_set_blocks(csp_ctx *ctx, int blocks);
 int csp_set_path(csp_ctx *ctx, int path);
 int csp_last_path(const csp_ctx *ctx);
 
+/* Cycle trace for later csp_solve_dev calls on ctx (off when cap = 0):
+ * trace is a device buffer of cap rows of four int64, one row per time at
+ * which water is delivered (section 4, Algorithm 1's loop): t, flows
+ * delivered at t, |I_t| (vertices whose label improved at t), flows sent
+ * from I_t.  The last row's "sent" is 0 (the run ends before sending).
+ * Rows beyond cap are counted but not written; csp_last_trace_rows gives
+ * the count of the last successful solve.  The trace needs the
+ * range-owned kernel (csp_set_path 0, 1 or 3); a solve that would take the
+ * global-label kernel returns CSP_EINVAL. */
+int csp_set_trace(csp_ctx *ctx, int64_t *trace, int64_t cap);
+int csp_last_trace_rows(const csp_ctx *ctx, int64_t *rows);
+
 /* Phase timing of the cycle kernel (off by default).  When on, workgroup 0
  * accumulates wall-clock time per phase; csp_last_phase_us fills us[6] with
  * microseconds spent in: departure work, the barrier after it, finding the

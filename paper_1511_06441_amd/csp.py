@@ -27,7 +27,7 @@ EXPORTED = (
     "csp_reconstruct_dev", "csp_last_kernel_ms", "csp_set_pool_hint",
     "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us", "csp_set_path",
     "csp_last_path", "csp_solve_batch", "csp_serve_open", "csp_serve_submit",
-    "csp_serve_poll", "csp_serve_pending", "csp_serve_close",
+    "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
 )
 
 
@@ -100,6 +100,10 @@ def _load():
     lib.csp_set_phase_timing.restype = i32
     lib.csp_last_phase_us.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
     lib.csp_last_phase_us.restype = i32
+    lib.csp_set_trace.argtypes = [p, p, i64]
+    lib.csp_set_trace.restype = i32
+    lib.csp_last_trace_rows.argtypes = [p, ctypes.POINTER(i64)]
+    lib.csp_last_trace_rows.restype = i32
     lib.csp_serve_open.argtypes = [p, ctypes.c_uint64, i32, ctypes.POINTER(p)]
     lib.csp_serve_open.restype = i32
     lib.csp_serve_submit.argtypes = [p, ctypes.POINTER(csp_request)]
@@ -234,6 +238,21 @@ PHASES = ("departure", "barrier_after_departure", "next_time", "arrival",
 
 def csp_set_phase_timing(ctx, on: bool):
     _check(ctx, lib.csp_set_phase_timing(ctx, 1 if on else 0))
+
+
+def csp_set_trace(ctx, trace=None):
+    """trace: device int64 tensor of shape (cap, 4), or None to switch the trace off."""
+    if trace is None:
+        _check(ctx, lib.csp_set_trace(ctx, None, 0))
+    else:
+        assert trace.dim() == 2 and trace.shape[1] == 4 and trace.is_contiguous()
+        _check(ctx, lib.csp_set_trace(ctx, ctypes.c_void_p(trace.data_ptr()), trace.shape[0]))
+
+
+def csp_last_trace_rows(ctx) -> int:
+    rows = ctypes.c_int64()
+    _check(ctx, lib.csp_last_trace_rows(ctx, ctypes.byref(rows)))
+    return rows.value
 
 
 def csp_last_phase_us(ctx) -> dict:

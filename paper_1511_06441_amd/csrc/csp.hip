@@ -52,6 +52,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -83,8 +84,9 @@ struct Out {
     long long res[5];              // T X x Y F2
     unsigned long long ctr[8];     // C U D E R P I
     unsigned long long prof[8];    // wall-clock ticks per phase (range 0)
+    long long trace_rows;          // cycle rows produced (may exceed the trace capacity)
     int status;
-    int pad[3];
+    int pad[1];
 };
 
 // State of one combining barrier among the g workgroups of a gang; the
@@ -962,6 +964,8 @@ struct RJ {
     long long max_cycles;
     unsigned long long wait_limit;
     int prof;
+    long long *trace;              // [trace_cap][4] per delivery cycle: t, delivered, |I_t|, sent (nullable)
+    long long trace_cap;
 };
 
 template <typename LT> __device__ __forceinline__ unsigned lab_get(const LT *lab, unsigned i) { return lab[i]; }
@@ -1133,7 +1137,11 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     };
 
     unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;      // per thread, committed
-    unsigned long long cC = 0, cP = 0, cI = 0;              // lead workgroup, thread 0, from the barrier
+    // counters C, P, I and the cycle trace state, kept by the lead's thread 0
+    // (in LDS, so they cost no registers): C P I | rows, in transit before the
+    // open row's sending round, its deliveries, open flag
+    __shared__ unsigned long long s_lc[7];
+    if (tid < 7) s_lc[tid] = 0;
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
     const bool timing = p.prof && lead && tid == 0;
 #define PHASE4(k)                                            \
@@ -1463,9 +1471,32 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             const unsigned long long a0 = all.rest ? ld64(&all.rest[0]) : all.s0;
             const unsigned long long a1 = all.rest ? ld64(&all.rest[1]) : all.s1;
             const unsigned long long a2 = all.rest ? ld64(&all.rest[2]) : all.s2;
-            cC += a0 > 0 ? 1 : 0;
-            cI = a1 > cI ? a1 : cI;
-            cP = a2 > cP ? a2 : cP;
+            s_lc[0] += a0 > 0 ? 1 : 0;
+            s_lc[2] = a1 > s_lc[2] ? a1 : s_lc[2];
+            s_lc[1] = a2 > s_lc[1] ? a2 : s_lc[1];
+            if (p.trace) {
+                // a0, a1: delivered and |I_t| at t; a2: in transit after the
+                // sending round of the previous cycle, which completes that
+                // cycle's row: sent = a2 - (in transit before it) + delivered
+                const long long rows = (long long)s_lc[3];
+                if (s_lc[6]) {
+                    if (rows <= p.trace_cap) p.trace[4 * (rows - 1) + 3] = (long long)(a2 - s_lc[4] + s_lc[5]);
+                    s_lc[6] = 0;
+                }
+                if (a0 > 0) {
+                    if (rows + 1 <= p.trace_cap) {
+                        long long *row = p.trace + 4 * rows;
+                        row[0] = t;
+                        row[1] = (long long)a0;
+                        row[2] = (long long)a1;
+                        row[3] = 0;             // the last row keeps 0: nothing is sent at the end
+                    }
+                    s_lc[3] = (unsigned long long)(rows + 1);
+                    s_lc[5] = a0;
+                    s_lc[6] = 1;
+                }
+                s_lc[4] = a2;
+            }
         }
         if (all.orf & SF_BHIT) {
             // ---- Step 6 (Algorithm 2): T = t.  The departure just made is
@@ -1675,9 +1706,10 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         if (s_red[3]) atomicAdd(&out->ctr[4], s_red[3]);
         if (lead) {
             for (int i = 0; i < 6; ++i) out->prof[i] = ph[i];
-            out->ctr[0] = cC;
-            out->ctr[5] = cP;
-            out->ctr[6] = cI;
+            out->ctr[0] = s_lc[0];
+            out->ctr[5] = s_lc[1];
+            out->ctr[6] = s_lc[2];
+            out->trace_rows = (long long)s_lc[3];
             const int br = __hip_atomic_load(&p.bar->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             out->status = br ? ST_BROKEN : status;
             if (status == ST_DONE && !found) {
@@ -2066,7 +2098,10 @@ struct csp_ctx {
     int prof = 0;
     unsigned long long pool_hint = 0;
     int blocks_override = 0;
-    int path_override = 0;          // 0 auto, 1 LDS ranges, 2 global labels
+    int path_override = 0;          // 0 auto, 1 LDS ranges, 2 global labels, 3 LDS pencils
+    long long *trace = nullptr;     // device [trace_cap][4], or null
+    long long trace_cap = 0;
+    long long last_trace_rows = 0;
     int last_path = 0;
     size_t lds_limit = 65536;
     unsigned *pub = nullptr;        // candidate fills [2][G][NOMAX]
@@ -2463,6 +2498,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     }
     const bool use_lds = plan.ok;
     if (use_lds) G = plan.G;
+    if (ctx->trace && !use_lds) return fail(ctx, CSP_EINVAL, "the cycle trace needs the range-owned kernel");
     ctx->last_path = use_lds ? 1 : 2;
 
     // wheel capacity: start from the largest a solve has needed, at least
@@ -2515,6 +2551,8 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             p.max_cycles = max_cycles;
             p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
             p.prof = ctx->prof;
+            p.trace = ctx->trace;
+            p.trace_cap = ctx->trace_cap;
             void *args[] = {&p};
             HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
             HIP_TRY(hipLaunchCooperativeKernel(lds_kernel(d, plan.tile), dim3(G), dim3(BLOCK), args,
@@ -2549,7 +2587,13 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(d), dim3(G), dim3(BLOCK), args, 0, s), "solve launch");
             HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
         }
-        HIP_TRY(hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "ctl copy");
+        {
+            // the results part of the control block: scalars, counters, result, Out
+            const size_t lo = offsetof(Ctl, xkey), hi = offsetof(Ctl, rbar);
+            HIP_TRY(hipMemcpyAsync(reinterpret_cast<uint8_t *>(ctx->h_ctl) + lo,
+                                   reinterpret_cast<const uint8_t *>(ctx->ctl) + lo, hi - lo, hipMemcpyDeviceToHost, s),
+                    "ctl copy");
+        }
         HIP_TRY(hipStreamSynchronize(s), "solve");
         const Ctl &c = *ctx->h_ctl;
         const int status = use_lds ? c.rout.status : c.status;
@@ -2576,6 +2620,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         }
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
         for (int i = 0; i < 8; ++i) ctx->last_prof[i] = prof[i];
+        ctx->last_trace_rows = use_lds ? c.rout.trace_rows : 0;
         out->T = res[0];
         out->X = res[1];
         out->x = res[2];
@@ -3418,6 +3463,21 @@ int csp_serve_close(csp_server *s)
     if (s->hpath) (void)hipHostFree(s->hpath);
     delete s;
     return rc;
+}
+
+int csp_set_trace(csp_ctx *ctx, int64_t *trace, int64_t cap)
+{
+    if (!ctx || cap < 0 || (cap > 0 && !trace)) return CSP_EINVAL;
+    ctx->trace = cap > 0 ? reinterpret_cast<long long *>(trace) : nullptr;
+    ctx->trace_cap = cap;
+    return CSP_OK;
+}
+
+int csp_last_trace_rows(const csp_ctx *ctx, int64_t *rows)
+{
+    if (!ctx || !rows) return CSP_EINVAL;
+    *rows = ctx->last_trace_rows;
+    return CSP_OK;
 }
 
 int csp_set_path(csp_ctx *ctx, int path)
