@@ -208,6 +208,26 @@ def algorithmic_bytes(N, c):
             + c["R"] * (FLOW_BYTES + 2 * L))
 
 
+def trace_summary(csp, solver, torch, di, points=16):
+    """Active set |I_t| and water in transit against t for one solve (outside
+    the timed region), sampled at `points` evenly spaced rows."""
+    cap = 1 << 20
+    tr = torch.zeros((cap, 4), dtype=torch.int64, device="cuda")
+    csp.csp_set_trace(solver.ctx, tr)
+    try:
+        res, cnt = solver.solve(di)
+        rows = min(csp.csp_last_trace_rows(solver.ctx), cap)
+    finally:
+        csp.csp_set_trace(solver.ctx, None)
+    a = tr[:rows].cpu().numpy()
+    sent0 = cnt.E - int(a[:, 3].sum())
+    transit = sent0 + (a[:, 3] - a[:, 1]).cumsum()
+    idx = sorted(set(int(round(k * (rows - 1) / (points - 1))) for k in range(points)))
+    return {"rows": rows, "T": res.T, "max_active": int(a[:, 2].max()), "t_max_active": int(a[a[:, 2].argmax(), 0]),
+            "max_transit": int(max(sent0, transit.max())),
+            "samples": [[int(a[k, 0]), int(a[k, 2]), int(transit[k])] for k in idx]}
+
+
 def measured_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, when it was taken on the current kernel source; else None."""
@@ -250,6 +270,8 @@ def main():
     ap.add_argument("--serve-arena-gb", type=int, default=64)
     ap.add_argument("--serve-fracs", type=float, nargs="*", default=[0.25, 0.5, 0.8])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--trace", action="store_true",
+                    help="also report |I_t| and water in transit against t (one extra solve each, untimed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the path does not shard "
@@ -328,6 +350,8 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if args.trace:
+        line["trace"] = [trace_summary(csp, solver, torch, di) for di in dev]
     if not args.no_cpu_baseline and wl["sample_index"] is not None:
         line["cpu_baseline"] = cpu_baseline(insts[wl["sample_index"]])
     print(json.dumps(line), flush=True)

@@ -115,6 +115,23 @@ int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n,
                         int64_t *path, int64_t cap, int64_t *len,
                         csp_result *out, void *stream);
 
+/* Path recovery with memory instead of re-solves (the trade-off section 1
+ * sets aside for memory): one solve that logs every label improvement
+ * (vertex, t, label and the improvement record of the sender of the best
+ * delivery, ties to the smallest sender), then a walk from X's record back
+ * to A.  The path, result and counters are identical to csp_reconstruct_dev
+ * and csp_solve_dev; path (host, cap entries) receives the vertices A -> X
+ * and *len their count (cap too small: CSP_EINVAL with *len set).  Extra
+ * device memory: 16 bytes per label improvement (U), 12 bytes per vertex,
+ * 4 bytes per wheel and candidate slot; it grows and retries like the
+ * wheel.  Needs the range-owned kernel (csp_set_path 0, 1 or 3).
+ * Synchronous on `stream`. */
+int csp_reconstruct_log_dev(csp_ctx *ctx, int d, int64_t n,
+                            const uint8_t *f1, const uint8_t *f2,
+                            const uint8_t *A, const uint8_t *B, uint32_t M,
+                            int64_t *path, int64_t cap, int64_t *len,
+                            csp_result *out, csp_counters *cnt, void *stream);
+
 /* One problem of a batch: device pointers laid out as for csp_solve_dev.
  * labels (nullable) is a device uint32 [n^d] output. */
 typedef struct {

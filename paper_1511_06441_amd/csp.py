@@ -28,6 +28,7 @@ EXPORTED = (
     "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us", "csp_set_path",
     "csp_last_path", "csp_solve_batch", "csp_serve_open", "csp_serve_submit",
     "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
+    "csp_reconstruct_log_dev",
 )
 
 
@@ -100,6 +101,9 @@ def _load():
     lib.csp_set_phase_timing.restype = i32
     lib.csp_last_phase_us.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
     lib.csp_last_phase_us.restype = i32
+    lib.csp_reconstruct_log_dev.argtypes = [p, i32, i64, p, p, p, p, u32, p, i64, ctypes.POINTER(i64),
+                                            ctypes.POINTER(csp_result), ctypes.POINTER(csp_counters), p]
+    lib.csp_reconstruct_log_dev.restype = i32
     lib.csp_set_trace.argtypes = [p, p, i64]
     lib.csp_set_trace.restype = i32
     lib.csp_last_trace_rows.argtypes = [p, ctypes.POINTER(i64)]
@@ -240,6 +244,20 @@ def csp_set_phase_timing(ctx, on: bool):
     _check(ctx, lib.csp_set_phase_timing(ctx, 1 if on else 0))
 
 
+def csp_reconstruct_log_dev(ctx, d, n, f1, f2, A, B, M, cap, stream=None):
+    """Path A -> X from one logged solve; returns (path int64 array, result, counters)."""
+    import numpy as np
+    path = np.zeros(max(int(cap), 1), dtype=np.int64)
+    ln = ctypes.c_int64()
+    res = csp_result()
+    cnt = csp_counters()
+    rc = lib.csp_reconstruct_log_dev(ctx, d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), M,
+                                     path.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(ln),
+                                     ctypes.byref(res), ctypes.byref(cnt), _stream(stream))
+    _check(ctx, rc)
+    return path[:ln.value].copy(), res, cnt
+
+
 def csp_set_trace(ctx, trace=None):
     """trace: device int64 tensor of shape (cap, 4), or None to switch the trace off."""
     if trace is None:
@@ -307,6 +325,10 @@ class Solver:
         return csp_solve_dev(self.ctx, di.d, di.n, di.f1, di.f2, di.A, di.B,
                              di.M if M is None else M, labels=labels,
                              max_cycles=max_cycles, stream=stream)
+
+    def reconstruct_log(self, di: DeviceInstance, cap=None, stream=None):
+        cap = cap if cap is not None else min(di.M, di.N) + 1
+        return csp_reconstruct_log_dev(self.ctx, di.d, di.n, di.f1, di.f2, di.A, di.B, di.M, cap, stream=stream)
 
     def reconstruct(self, di: DeviceInstance, scratch_mask, cap=None, stream=None):
         cap = cap if cap is not None else di.N + 1

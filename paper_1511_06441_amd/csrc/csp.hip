@@ -85,6 +85,7 @@ struct Out {
     unsigned long long ctr[8];     // C U D E R P I
     unsigned long long prof[8];    // wall-clock ticks per phase (range 0)
     long long trace_rows;          // cycle rows produced (may exceed the trace capacity)
+    long long xrec;                // improvement record of X at T (logging runs)
     int status;
     int pad[1];
 };
@@ -966,6 +967,13 @@ struct RJ {
     int prof;
     long long *trace;              // [trace_cap][4] per delivery cycle: t, delivered, |I_t|, sent (nullable)
     long long trace_cap;
+    // improvement log (reconstruction by walking back instead of re-solving)
+    unsigned *wptr;                // [pool] record of the sender of each wheel flow
+    unsigned *cptr;                // [2][g][NO][cand_cap] record of the sender of each candidate
+    unsigned long long *winner;    // [g][c] (quality, -direction, sender record) of the best delivery
+    unsigned *cur;                 // [g][c] latest improvement record of each vertex
+    uint4 *log;                    // [g][log_cap] records (parent record, vertex, t, label)
+    unsigned long long log_cap;    // records per range
 };
 
 template <typename LT> __device__ __forceinline__ unsigned lab_get(const LT *lab, unsigned i) { return lab[i]; }
@@ -1047,7 +1055,7 @@ struct RunRes {
 // initialisation (reinit_mf == 0) writes it; a later solve of the same
 // lattice passes the largest f1 seen before as reinit_mf and starts from
 // abits, without re-reading or re-packing the edges.
-template <int D, bool TILE = false>
+template <int D, bool TILE = false, bool LOG = false>
 __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M, long long bvert, unsigned &epoch,
                             Out *out, unsigned *abits = nullptr, unsigned reinit_mf = 0)
 {
@@ -1306,6 +1314,37 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
 
     unsigned nlist = compact();
     if (tid == 0) cU += nlist;
+    // improvement log: this range's records are log[r * log_cap ...]
+    __shared__ unsigned long long s_logn;
+    const unsigned long long logbase = LOG ? (unsigned long long)r * p.log_cap : 0;
+    auto log_improved = [&](long long tt, unsigned nl, bool first) {
+        // one record per vertex of I_t, parent = sender record of its best delivery
+        const unsigned long long used = s_logn;
+        if (used + nl > p.log_cap) {
+            if (tid == 0) atomicOr(&s_flags, SF_OVER);
+            return;
+        }
+        for (unsigned j = tid; j < nl; j += BLOCK) {
+            const unsigned i = list_get(j);
+            // the best delivery was combined by atomics in L2: read it there
+            const unsigned parent =
+                first ? 0xFFFFFFFFu
+                      : (unsigned)(__hip_atomic_load(&p.winner[base + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                                   0xFFFFFFFFull);
+            const unsigned idx = (unsigned)(logbase + used + j);
+            p.log[idx] = make_uint4(parent, (unsigned)gvert(i), (unsigned)tt, lget(lab, l16, i));
+            p.cur[base + i] = idx;
+        }
+        __syncthreads();
+        if (tid == 0) s_logn = used + nl;
+        __syncthreads();
+    };
+    if constexpr (LOG) {
+        for (unsigned i = tid; i < (unsigned)c; i += BLOCK) p.winner[base + i] = 0;
+        if (tid == 0) s_logn = 0;
+        __syncthreads();
+        log_improved(0, nlist, true);
+    }
 
     int status = ST_RUNNING;
     unsigned W = 2;
@@ -1327,6 +1366,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     const unsigned long long S = p.pool_flows / ((unsigned long long)G * W);
     const unsigned CS = p.cand_cap;
     uint2 *wheel = p.pool + (unsigned long long)r * W * S;
+    unsigned *wptr = LOG ? p.wptr + (unsigned long long)r * W * S : nullptr;
 
     rr.X = rr.LX = 0;
     long long t = 0, t_prev = 0;
@@ -1363,6 +1403,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             front(j + 2 * BLOCK, i2, r2);
             fb[i >> 5] = 0;                 // every vertex of the word is in this list
             const unsigned L = lget(lab, l16, i);
+            const unsigned myrec = LOG ? p.cur[base + i] : 0u;
 #pragma unroll
             for (int dir = 0; dir < 2 * D; ++dir) {
                 unsigned a1, a2;
@@ -1399,11 +1440,13 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                     if ((unsigned)q > lget(lab, l16, li)) {
                         const unsigned bk = (unsigned)((t + a1) & Wm);
                         const unsigned pos = atomicAdd(&cnt[bk], 1u);
-                        if (pos < S)
+                        if (pos < S) {
                             wheel[(unsigned long long)bk * S + pos] =
                                 make_uint2((unsigned)(base + li), ((unsigned)q << 3) | rdir);
-                        else
+                            if constexpr (LOG) wptr[(unsigned long long)bk * S + pos] = myrec;
+                        } else {
                             atomicOr(&s_flags, SF_OVER);
+                        }
                         ++dE;
                     }
                 } else {
@@ -1417,10 +1460,12 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                     if ((int)lane == leader) first = atomicAdd(&s_ccnt[oi], (unsigned)__popcll(grp));
                     first = __shfl(first, leader);
                     const unsigned pos = first + (unsigned)__popcll(grp & ((1ull << lane) - 1ull));
-                    if (pos < CS)
+                    if (pos < CS) {
                         candbuf(par, r, oi)[pos] = make_uint2(li | (a1 << 17) | (rdir << 25), (unsigned)q);
-                    else
+                        if constexpr (LOG) p.cptr[(candbuf(par, r, oi) - cand) + pos] = myrec;
+                    } else {
                         atomicOr(&s_flags, SF_OVER);
+                    }
                     amin = a1 < amin ? a1 : amin;
                 }
             }
@@ -1531,6 +1576,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                         out->res[2] = (long long)k * N + (lower ? Y : (long long)X);
                         out->res[3] = Y;
                         out->res[4] = (long long)M - (long long)LX;
+                        if constexpr (LOG) out->xrec = p.cur[base + xl];
                     }
                 }
             }
@@ -1569,6 +1615,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             constexpr int UC = 4;                   // candidate loads in flight per thread
             for (unsigned j0 = tid; j0 < FC; j0 += BLOCK * UC) {
               uint2 cdu[UC];
+              unsigned cpu[UC];
 #pragma unroll
               for (int u = 0; u < UC; ++u) {
                 const unsigned j = j0 + u * BLOCK;
@@ -1576,7 +1623,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                     int oi = 0;
                     while (j >= s_cpre[oi + 1]) ++oi;
                     const long long src = (long long)r - soff(oi);
-                    cdu[u] = candbuf(par, (unsigned long long)src, (unsigned)oi)[j - s_cpre[oi]];
+                    const uint2 *cb = candbuf(par, (unsigned long long)src, (unsigned)oi);
+                    cdu[u] = cb[j - s_cpre[oi]];
+                    if constexpr (LOG) cpu[u] = p.cptr[(cb - cand) + (j - s_cpre[oi])];
                 }
               }
 #pragma unroll
@@ -1587,10 +1636,12 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 if (cd.y > lget(lab, l16, li)) {
                     const unsigned bk = (unsigned)((t_prev + a1) & Wm);
                     const unsigned pos = atomicAdd(&cnt[bk], 1u);
-                    if (pos < S)
+                    if (pos < S) {
                         wheel[(unsigned long long)bk * S + pos] = make_uint2((unsigned)(base + li), (cd.y << 3) | rdir);
-                    else
+                        if constexpr (LOG) wptr[(unsigned long long)bk * S + pos] = cpu[u];
+                    } else {
                         atomicOr(&s_flags, SF_OVER);
+                    }
                     ++cE;
                 }
               }
@@ -1622,16 +1673,27 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             constexpr int UA = 4;                   // flow loads in flight per thread
             for (unsigned j0 = tid; j0 < F; j0 += BLOCK * UA) {
                 uint2 f[UA];
+                unsigned fp[UA];
 #pragma unroll
                 for (int u = 0; u < UA; ++u) {
                     const unsigned j = j0 + u * BLOCK;
-                    if (j < F) f[u] = bkt[j];
+                    if (j < F) {
+                        f[u] = bkt[j];
+                        if constexpr (LOG) fp[u] = wptr[(unsigned long long)bk * S + j];
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < UA; ++u) {
                     if (j0 + u * BLOCK < F) {
                         const unsigned i = (unsigned)((long long)f[u].x - base);
-                        if (lraise(lab, l16, i, f[u].y >> 3)) {
+                        const bool raised = lraise(lab, l16, i, f[u].y >> 3);
+                        if constexpr (LOG) {
+                            const unsigned q = f[u].y >> 3;
+                            if (q >= lget(lab, l16, i))
+                                atomicMax(&p.winner[base + i], ((unsigned long long)q << 35) |
+                                                                   ((unsigned long long)(7u - (f[u].y & 7u)) << 32) | fp[u]);
+                        }
+                        if (raised) {
                             // the first raise of a vertex this cycle puts it in I_t
                             const unsigned bit = 1u << (i & 31);
                             if (!(atomicOr(&fb[i >> 5], bit) & bit)) {
@@ -1677,6 +1739,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             }
             __syncthreads();
             transit = s_sum;
+            if constexpr (LOG) log_improved(t, nlist, false);
         }
         PHASE4(3);
     }
@@ -1728,14 +1791,31 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
 
 // Single solve: the whole grid is one gang; range r of physical block b is
 // chosen so that each XCD (blocks b = x mod 8) holds a contiguous run.
-template <int D, bool TILE = false>
+template <int D, bool TILE = false, bool LOG = false>
 __global__ void __launch_bounds__(BLOCK) k_ranges(RJ p)
 {
     extern __shared__ unsigned smem[];
     const unsigned G = gridDim.x;
     const unsigned r = (G % NGRP) == 0 ? (blockIdx.x % NGRP) * (G / NGRP) + blockIdx.x / NGRP : blockIdx.x;
     unsigned epoch = 0;
-    (void)range_run<D, TILE>(p, r, smem, p.M, -1, epoch, p.out);
+    (void)range_run<D, TILE, LOG>(p, r, smem, p.M, -1, epoch, p.out);
+}
+
+// Path of a logged solve, from X back to A: follow the parent records.
+// Stops after cap vertices (a path never has more than min(M, N)) or at a
+// record index outside the log (then *len = -1).
+__global__ void k_walk(const uint4 *log, unsigned long long nlog, long long xrec, long long *path, long long cap,
+                       long long *len)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    long long k = 0;
+    unsigned idx = (unsigned)xrec;
+    while (k < cap && idx != 0xFFFFFFFFu && idx < nlog) {
+        const uint4 rec = log[idx];
+        path[k++] = rec.y;
+        idx = rec.x;
+    }
+    *len = idx == 0xFFFFFFFFu ? k : -1;
 }
 
 // Batched solves in one persistent launch.  Work is a list of (job, range)
@@ -2108,6 +2188,17 @@ struct csp_ctx {
     size_t pub_cap = 0;
     uint2 *cand = nullptr;          // candidates [2][G][NO][cap]
     size_t cand_cap = 0;
+    // improvement log (csp_reconstruct_log_dev)
+    unsigned *wptr = nullptr, *cptr = nullptr, *cur = nullptr;
+    size_t wptr_cap = 0, cptr_cap = 0, cur_cap = 0;
+    unsigned long long *winner = nullptr;
+    size_t winner_cap = 0;
+    uint4 *logbuf = nullptr;
+    size_t logbuf_cap = 0;
+    unsigned long long log_seen = 0;   // records per range a logged solve needed so far
+    long long *walk = nullptr;         // [cap + 1] path from X back, then its length
+    size_t walk_cap = 0;
+    long long last_xrec = -1;
     unsigned long long cand_seen = 0;
     unsigned long long pool_flows_seen = 0;   // largest pool a solve needed so far
     uint8_t *arena = nullptr;       // batch: per-problem device state
@@ -2149,8 +2240,16 @@ int grow(csp_ctx *ctx, T **p, size_t &cap, size_t need, const char *what)
     return CSP_OK;
 }
 
-const void *lds_kernel(int d, int tile)
+const void *lds_kernel(int d, int tile, bool log = false)
 {
+    if (log) {
+        switch (d) {
+        case 1: return (const void *)k_ranges<1, false, true>;
+        case 2: return (const void *)k_ranges<2, false, true>;
+        case 3: return tile ? (const void *)k_ranges<3, true, true> : (const void *)k_ranges<3, false, true>;
+        default: return (const void *)k_ranges<4, false, true>;
+        }
+    }
     switch (d) {
     case 1: return (const void *)k_ranges<1>;
     case 2: return (const void *)k_ranges<2>;
@@ -2454,9 +2553,13 @@ const char *csp_last_error(const csp_ctx *ctx)
     return ctx ? ctx->err : "no context";
 }
 
-int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
-                  const uint8_t *A, const uint8_t *B, uint32_t M, uint32_t *labels,
-                  csp_result *out, csp_counters *cnt, int64_t max_cycles, void *stream)
+}  // extern "C"
+
+namespace {
+
+int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2, const uint8_t *A,
+               const uint8_t *B, uint32_t M, uint32_t *labels, csp_result *out, csp_counters *cnt,
+               int64_t max_cycles, void *stream, bool log)
 {
     if (!ctx || !out || !f1 || !f2 || !A || !B) return fail(ctx, CSP_EINVAL, "null argument");
     long long N = 0;
@@ -2485,7 +2588,7 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     if (ctx->path_override != 2) {
         plan = plan_lds(ctx, d, n, N, M, G);
         if (plan.ok) {
-            const void *kf = lds_kernel(d, plan.tile);
+            const void *kf = lds_kernel(d, plan.tile, log);
             if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds) != hipSuccess)
                 plan.ok = false;
             int nb = 0;
@@ -2499,6 +2602,9 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     const bool use_lds = plan.ok;
     if (use_lds) G = plan.G;
     if (ctx->trace && !use_lds) return fail(ctx, CSP_EINVAL, "the cycle trace needs the range-owned kernel");
+    if (log && !use_lds) return fail(ctx, CSP_EINVAL, "the improvement log needs the range-owned kernel");
+    // log records per range: at least two per vertex, else what a solve needed before
+    unsigned long long log_cap = log ? std::max<unsigned long long>(2ull * plan.c, ctx->log_seen) : 0ull;
     ctx->last_path = use_lds ? 1 : 2;
 
     // wheel capacity: start from the largest a solve has needed, at least
@@ -2536,6 +2642,14 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             if (rc) return rc;
             rc = grow(ctx, &ctx->cand, ctx->cand_cap, (size_t)(2ull * G * NO * ccap), "candidates");
             if (rc) return rc;
+            if (log) {
+                rc = grow(ctx, &ctx->wptr, ctx->wptr_cap, (size_t)pool, "log: wheel senders");
+                if (!rc) rc = grow(ctx, &ctx->cptr, ctx->cptr_cap, (size_t)(2ull * G * NO * ccap), "log: candidate senders");
+                if (!rc) rc = grow(ctx, &ctx->cur, ctx->cur_cap, (size_t)(plan.c * G), "log: latest records");
+                if (!rc) rc = grow(ctx, &ctx->winner, ctx->winner_cap, (size_t)(plan.c * G), "log: best deliveries");
+                if (!rc) rc = grow(ctx, &ctx->logbuf, ctx->logbuf_cap, (size_t)(log_cap * G), "log: records");
+                if (rc) return rc;
+            }
             RJ p;
             fill_job(p, d, n, N, plan, f1, f2, A, B, M);
             p.rec = ctx->rec;
@@ -2553,9 +2667,17 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             p.prof = ctx->prof;
             p.trace = ctx->trace;
             p.trace_cap = ctx->trace_cap;
+            if (log) {
+                p.wptr = ctx->wptr;
+                p.cptr = ctx->cptr;
+                p.cur = ctx->cur;
+                p.winner = ctx->winner;
+                p.log = ctx->logbuf;
+                p.log_cap = log_cap;
+            }
             void *args[] = {&p};
             HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
-            HIP_TRY(hipLaunchCooperativeKernel(lds_kernel(d, plan.tile), dim3(G), dim3(BLOCK), args,
+            HIP_TRY(hipLaunchCooperativeKernel(lds_kernel(d, plan.tile, log), dim3(G), dim3(BLOCK), args,
                                                (unsigned)plan.lds, s),
                     "solve launch");
             HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
@@ -2604,11 +2726,16 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
             return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0, or A and B overlap");
         }
         if (status == ST_OVERFLOW) {
-            if (pool >= pool_max && ccap >= cand_max)
+            if (pool >= pool_max && ccap >= cand_max && !log)
                 return fail(ctx, CSP_EOVERFLOW, "transit pool overflow at the edge bound");
             pool = std::min(pool * 2, pool_max);
             qs = std::min<unsigned long long>(qs * 2, (unsigned long long)N);
             ccap = std::min(ccap * 2, cand_max);
+            if (log) {
+                log_cap *= 2;
+                if (log_cap * (unsigned long long)G >= (1ull << 32))
+                    return fail(ctx, CSP_EOVERFLOW, "improvement log beyond 2^32 records");
+            }
             continue;
         }
         if (status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
@@ -2621,6 +2748,8 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
         for (int i = 0; i < 8; ++i) ctx->last_prof[i] = prof[i];
         ctx->last_trace_rows = use_lds ? c.rout.trace_rows : 0;
+        ctx->last_xrec = log ? c.rout.xrec : -1;
+        if (log && !ctx->pool_hint) ctx->log_seen = std::max(ctx->log_seen, log_cap);
         out->T = res[0];
         out->X = res[1];
         out->x = res[2];
@@ -2637,6 +2766,51 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
         }
         return CSP_OK;
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
+                  const uint8_t *A, const uint8_t *B, uint32_t M, uint32_t *labels,
+                  csp_result *out, csp_counters *cnt, int64_t max_cycles, void *stream)
+{
+    return solve_impl(ctx, d, n, f1, f2, A, B, M, labels, out, cnt, max_cycles, stream, false);
+}
+
+int csp_reconstruct_log_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
+                            const uint8_t *A, const uint8_t *B, uint32_t M, int64_t *path, int64_t cap,
+                            int64_t *len, csp_result *out, csp_counters *cnt, void *stream)
+{
+    if (!ctx || !path || !len || !out) return fail(ctx, CSP_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    *len = 0;
+    int rc = solve_impl(ctx, d, n, f1, f2, A, B, M, nullptr, out, cnt, 0, stream, true);
+    if (rc) return rc;
+    if (out->T < 0) return CSP_OK;
+    long long N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    // a path has at most min(M, N) vertices
+    const long long wcap = std::min<long long>((long long)M, N);
+    rc = grow(ctx, &ctx->walk, ctx->walk_cap, (size_t)wcap + 1, "path walk");
+    if (rc) return rc;
+    if (ctx->last_xrec < 0 || (size_t)ctx->last_xrec >= ctx->logbuf_cap)
+        return fail(ctx, CSP_EDEVICE, "no improvement record for X");
+    hipLaunchKernelGGL(k_walk, dim3(1), dim3(64), 0, s, (const uint4 *)ctx->logbuf,
+                       (unsigned long long)ctx->logbuf_cap, ctx->last_xrec, ctx->walk, wcap, ctx->walk + wcap);
+    HIP_TRY(hipGetLastError(), "walk launch");
+    long long L = 0;
+    HIP_TRY(hipMemcpyAsync(&L, ctx->walk + wcap, sizeof(L), hipMemcpyDeviceToHost, s), "walk length");
+    HIP_TRY(hipStreamSynchronize(s), "walk");
+    if (L < 2) return fail(ctx, CSP_EDEVICE, "improvement log did not lead back to A");
+    *len = L;
+    if (L > cap) return fail(ctx, CSP_EINVAL, "path buffer too small");
+    HIP_TRY(hipMemcpyAsync(path, ctx->walk, (size_t)L * sizeof(long long), hipMemcpyDeviceToHost, s), "walk copy");
+    HIP_TRY(hipStreamSynchronize(s), "walk copy");
+    std::reverse(path, path + L);
+    if (path[L - 1] != out->X || path[L - 2] != out->Y) return fail(ctx, CSP_EDEVICE, "logged path disagrees with x");
+    return CSP_OK;
 }
 
 int csp_solve(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2,

@@ -311,3 +311,63 @@ def test_reconstruct_vs_oracle(solver, torch, case):
     assert res.tuple() == res_ref.tuple()
     assert path.tolist() == path_ref.tolist()
     assert int(scratch.sum().item()) == 0
+
+
+# ---------------------------------------------------------------------------
+# path recovery from the improvement log (one solve, then a walk back)
+# ---------------------------------------------------------------------------
+
+LOG_CASES = [(2, 12, 1, 5, 5, 50), (3, 6, 3, 10, 10, 60), (2, 64, 2, 5, 5, 200), (3, 16, 4, 10, 10, 150),
+             (2, 150, 6, 20, 20, 900), (3, 40, 8, 3, 3, 200), (2, 40, 9, 1, 1, 100)]
+
+
+@pytest.mark.parametrize("case", LOG_CASES)
+@pytest.mark.parametrize("blocks,path", [(0, 0), (16, 1), (16, 3)])
+def test_reconstruct_log_vs_oracle(solver, torch, case, blocks, path):
+    """The logged walk gives the oracle's repeated-solve path, result and counters."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    d, n, seed, K1, K2, M = case
+    inst = gen.opposite_faces(d, n, seed, K1, K2, M)
+    _say("case", inst.name, "blocks", blocks, "path", path)
+    path_ref, res_ref, _ = O.reconstruct(d, n, inst.f1, inst.f2, inst.A, inst.B, M)
+    ref = _oracle(inst)
+    di = csp.to_device(inst)
+    csp.csp_set_blocks(solver.ctx, blocks)
+    csp.csp_set_path(solver.ctx, path)
+    try:
+        got, res, cnt = solver.reconstruct_log(di)
+    finally:
+        csp.csp_set_blocks(solver.ctx, 0)
+        csp.csp_set_path(solver.ctx, 0)
+    assert res.tuple() == res_ref.tuple() == ref.tuple()
+    assert cnt.asdict() == ref.counters
+    assert got.tolist() == path_ref.tolist()
+
+
+@pytest.mark.parametrize("which", ["cube128", "paper75"])
+def test_reconstruct_log_equals_repeated_solves_full_size(solver, torch, which):
+    from paper_1511_06441_amd import csp
+    inst = gen.cube128(11, 700) if which == "cube128" else gen.cube_boundary_to_center(75, 61, K=100, M=10000)
+    _say("case", inst.name)
+    di = csp.to_device(inst)
+    got, res, cnt = solver.reconstruct_log(di)
+    scratch = torch.zeros(inst.N, dtype=torch.uint8, device="cuda")
+    path, res2 = solver.reconstruct(di, scratch)
+    assert res.tuple() == res2.tuple()
+    assert got.tolist() == path.tolist()
+    _say("  path vertices", len(got))
+
+
+def test_reconstruct_log_retries_small_log(solver, torch):
+    """A one-flow wheel also shrinks the starting log: retries give the same path."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    inst = gen.opposite_faces(3, 24, 9, 6, 6, 150)
+    path_ref, res_ref, _ = O.reconstruct(3, 24, inst.f1, inst.f2, inst.A, inst.B, 150)
+    csp.csp_set_pool_hint(solver.ctx, 1)
+    try:
+        got, res, cnt = solver.reconstruct_log(csp.to_device(inst))
+    finally:
+        csp.csp_set_pool_hint(solver.ctx, 0)
+    assert res.tuple() == res_ref.tuple() and got.tolist() == path_ref.tolist()
