@@ -199,6 +199,54 @@ def run_serve(args):
     print(json.dumps(line), flush=True)
 
 
+RECON_DESC = ("path recovery on cube128 (seed 11, M=700) and a 2-D 1016^2 lattice (serving request 3 of master "
+              "seed 51: f1,f2 U{1..10}, M=10989): repeated solves (host-driven, one csp_solve_dev per path edge) "
+              "against one solve with the improvement log and a walk back")
+
+
+def run_recon(args):
+    import torch
+    from paper_1511_06441_amd import csp
+    from paper_1511_06441_amd import inputs as gen
+
+    s, d, n, K, M = gen.serving_params(4, 51)[3]
+    insts = [("cube128_s11_M700", csp.to_device(gen.cube128(11, 700))),
+             (f"square{n}_s51_3", csp.DeviceInstance(d, n, *gen.lattice_edges_torch(d, n, s, K, K, device="cuda"),
+                                                     gen.face_mask_torch(d, n, 0, 0, "cuda"),
+                                                     gen.face_mask_torch(d, n, 0, n - 1, "cuda"), M))]
+    torch.cuda.synchronize()
+    solver = csp.Solver(0)
+    out = []
+    for name, di in insts:
+        solver.reconstruct_log(di)                      # warm-up (sizes the log)
+        scratch = torch.zeros(di.N, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_rep, r_rep = solver.reconstruct(di, scratch)
+        torch.cuda.synchronize()
+        t_rep = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        reps = max(1, args.steps)
+        for _ in range(reps):
+            p_log, r_log, c_log = solver.reconstruct_log(di)
+        torch.cuda.synchronize()
+        t_log = (time.perf_counter() - t0) / reps
+        out.append({"instance": name, "path_vertices": len(p_log), "T": r_log.T, "F2": r_log.F2,
+                    "repeated_solves_s": t_rep, "logged_s": t_log, "speedup": t_rep / t_log,
+                    "paths_equal": p_rep.tolist() == p_log.tolist() and r_rep.tuple() == r_log.tuple(),
+                    "log_records": c_log.U})
+        print(f"# {name}: repeated {t_rep:.3f} s, logged {t_log * 1e3:.1f} ms, {len(p_log)} vertices",
+              file=sys.stderr, flush=True)
+    line = {"metric": "path recoveries/s", "value": len(out) / sum(o["logged_s"] for o in out),
+            "unit": "recoveries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": sum(o["logged_s"] for o in out) * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded splitmix64 lattices)",
+            "config": {"workload": "recon", "desc": RECON_DESC, "parallelism": "single GPU"},
+            "results": out, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+    solver.close()
+
+
 def algorithmic_bytes(N, c):
     """Bytes the method must move for one solve (label init, own label per
     improvement, f1+f2+neighbour label per test, one flow record written per
@@ -263,7 +311,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["batch1024", "serve"])
+    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["batch1024", "serve", "recon"])
     ap.add_argument("--batch-count", type=int, default=1024)
     ap.add_argument("--plain", action="store_true", help="batch workload: also time sequential plain launches")
     ap.add_argument("--serve-count", type=int, default=32)
@@ -283,6 +331,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "recon":
+        run_recon(args)
         return
 
     import torch

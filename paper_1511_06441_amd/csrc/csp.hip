@@ -87,7 +87,7 @@ struct Out {
     long long trace_rows;          // cycle rows produced (may exceed the trace capacity)
     long long xrec;                // improvement record of X at T (logging runs)
     int status;
-    int pad[1];
+    int log_over;                  // the improvement log ran out (logging runs)
 };
 
 // State of one combining barrier among the g workgroups of a gang; the
@@ -1321,7 +1321,10 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         // one record per vertex of I_t, parent = sender record of its best delivery
         const unsigned long long used = s_logn;
         if (used + nl > p.log_cap) {
-            if (tid == 0) atomicOr(&s_flags, SF_OVER);
+            if (tid == 0) {
+                atomicOr(&s_flags, SF_OVER);
+                atomicOr(&out->log_over, 1);
+            }
             return;
         }
         for (unsigned j = tid; j < nl; j += BLOCK) {
@@ -2725,17 +2728,19 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
         if (status == ST_INVAL || (!use_lds && c.bad)) {
             return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0, or A and B overlap");
         }
+        if (status == ST_OVERFLOW && log && use_lds && c.rout.log_over) {
+            // only the log ran out
+            log_cap *= 2;
+            if (log_cap * (unsigned long long)G >= (1ull << 32))
+                return fail(ctx, CSP_EOVERFLOW, "improvement log beyond 2^32 records");
+            continue;
+        }
         if (status == ST_OVERFLOW) {
-            if (pool >= pool_max && ccap >= cand_max && !log)
+            if (pool >= pool_max && ccap >= cand_max)
                 return fail(ctx, CSP_EOVERFLOW, "transit pool overflow at the edge bound");
             pool = std::min(pool * 2, pool_max);
             qs = std::min<unsigned long long>(qs * 2, (unsigned long long)N);
             ccap = std::min(ccap * 2, cand_max);
-            if (log) {
-                log_cap *= 2;
-                if (log_cap * (unsigned long long)G >= (1ull << 32))
-                    return fail(ctx, CSP_EOVERFLOW, "improvement log beyond 2^32 records");
-            }
             continue;
         }
         if (status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
