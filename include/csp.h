@@ -115,6 +115,21 @@ int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n,
                         int64_t *path, int64_t cap, int64_t *len,
                         csp_result *out, void *stream);
 
+/* The same cycle on a general graph (section 1 states the problem for any
+ * graph with positive integer f1, f2; the lattice is the case the paper
+ * studies).  Device arrays: off int64 [nv+1] and, for each directed
+ * adjacency entry j (both directions of every edge present, neighbours of
+ * a vertex in ascending order), nbr int32 [m], f1 and f2 uint8 [m] (1..255),
+ * eid int64 [m] (the edge id reported as x; equal on the two copies of an
+ * edge); A, B uint8 [nv]; labels uint32 [nv] (nullable).  m = off[nv].
+ * Results, counters and errors as for csp_solve_dev; x is eid of the last
+ * edge.  Labels live in HBM (no LDS ranges). */
+int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off,
+                        const int32_t *nbr, const uint8_t *f1, const uint8_t *f2,
+                        const int64_t *eid, const uint8_t *A, const uint8_t *B,
+                        uint32_t M, uint32_t *labels, csp_result *out,
+                        csp_counters *cnt, int64_t max_cycles, void *stream);
+
 /* Path recovery with memory instead of re-solves (the trade-off section 1
  * sets aside for memory): one solve that logs every label improvement
  * (vertex, t, label and the improvement record of the sender of the best

@@ -28,7 +28,7 @@ EXPORTED = (
     "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us", "csp_set_path",
     "csp_last_path", "csp_solve_batch", "csp_serve_open", "csp_serve_submit",
     "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
-    "csp_reconstruct_log_dev",
+    "csp_reconstruct_log_dev", "csp_solve_graph_dev",
 )
 
 
@@ -104,6 +104,9 @@ def _load():
     lib.csp_reconstruct_log_dev.argtypes = [p, i32, i64, p, p, p, p, u32, p, i64, ctypes.POINTER(i64),
                                             ctypes.POINTER(csp_result), ctypes.POINTER(csp_counters), p]
     lib.csp_reconstruct_log_dev.restype = i32
+    lib.csp_solve_graph_dev.argtypes = [p, i64, p, p, p, p, p, p, p, u32, p, ctypes.POINTER(csp_result),
+                                        ctypes.POINTER(csp_counters), i64, p]
+    lib.csp_solve_graph_dev.restype = i32
     lib.csp_set_trace.argtypes = [p, p, i64]
     lib.csp_set_trace.restype = i32
     lib.csp_last_trace_rows.argtypes = [p, ctypes.POINTER(i64)]
@@ -256,6 +259,34 @@ def csp_reconstruct_log_dev(ctx, d, n, f1, f2, A, B, M, cap, stream=None):
                                      ctypes.byref(res), ctypes.byref(cnt), _stream(stream))
     _check(ctx, rc)
     return path[:ln.value].copy(), res, cnt
+
+
+@dataclass
+class DeviceGraph:
+    """A general graph's adjacency arrays in device memory (torch tensors)."""
+    nv: int
+    off: object      # int64 [nv+1]
+    nbr: object      # int32 [m]
+    f1: object       # uint8 [m]
+    f2: object       # uint8 [m]
+    eid: object      # int64 [m]
+
+
+def graph_to_device(csr, device="cuda"):
+    import torch
+    off, nbr, f1, f2, eid = csr
+    t = lambda a: torch.from_numpy(a).to(device)
+    return DeviceGraph(int(off.size - 1), t(off), t(nbr), t(f1), t(f2), t(eid))
+
+
+def csp_solve_graph_dev(ctx, g: DeviceGraph, A, B, M, labels=None, max_cycles=0, counters=True, stream=None):
+    res = csp_result()
+    cnt = csp_counters() if counters else None
+    rc = lib.csp_solve_graph_dev(ctx, g.nv, _ptr(g.off), _ptr(g.nbr), _ptr(g.f1), _ptr(g.f2), _ptr(g.eid),
+                                 _ptr(A), _ptr(B), M, _ptr(labels), ctypes.byref(res),
+                                 ctypes.byref(cnt) if counters else None, max_cycles, _stream(stream))
+    _check(ctx, rc)
+    return res, cnt
 
 
 def csp_set_trace(ctx, trace=None):

@@ -2131,6 +2131,321 @@ __global__ void __launch_bounds__(BLOCK) k_serve(ServeArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// General bounded-degree graphs (section 1 poses the problem on any graph;
+// the lattice is the case studied).  Adjacency lists replace the lattice
+// arithmetic: off[v] .. off[v+1] index nbr, f1, f2 and the edge id of each
+// directed entry (both directions of every edge present).  Labels live in
+// HBM and are raised with atomicMax; each workgroup files the flows it sends
+// in its own wheel segment and keeps the list of vertices it improved.  A
+// flow is (destination, quality, sender, adjacency entry), so the last edge
+// x and its sender Y come out of the bucket delivered at T.  Per cycle: an
+// arrival phase, a barrier (so departures read every delivery of t), the
+// departure phase, and a combining barrier that returns the next time, the
+// best B key and the counts.
+// ---------------------------------------------------------------------------
+
+struct GJ {
+    long long nv, m;
+    const long long *off;
+    const int *nbr;
+    const uint8_t *f1, *f2;
+    const long long *eid;
+    const uint8_t *A, *B;
+    unsigned M;
+    unsigned *lab;                 // [nv]
+    unsigned *stamp;               // [nv] cycle in which the vertex last joined an improved set
+    unsigned *lists;               // [2][G][qcap]
+    unsigned long long qcap;
+    uint4 *pool;                   // [G][W][S] flows (dst, q, sender, adjacency entry)
+    unsigned long long pool_flows;
+    BarHdr *bar;
+    Out *out;
+    unsigned long long *xsel;      // (sender << 32 | entry) of x, by atomicMin
+    unsigned *labels_out;
+    long long max_cycles;
+    unsigned long long wait_limit;
+};
+
+__global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
+{
+    __shared__ unsigned s_cnt[MAXW];
+    __shared__ unsigned s_nl, s_flags, s_min, s_mf;
+    __shared__ unsigned long long s_xkey, s_red[4];
+    __shared__ unsigned long long s_lc[3];          // lead: C, P, I
+    const unsigned tid = threadIdx.x, lane = lane_id();
+    const unsigned G = gridDim.x;
+    const unsigned r = (G % NGRP) == 0 ? (blockIdx.x % NGRP) * (G / NGRP) + blockIdx.x / NGRP : blockIdx.x;
+    const bool lead = r == 0;
+    const long long nv = p.nv;
+    unsigned epoch = 0;
+    unsigned *list[2] = {p.lists + (unsigned long long)r * p.qcap,
+                         p.lists + ((unsigned long long)G + r) * p.qcap};
+    unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;
+
+    for (unsigned i = tid; i < MAXW; i += BLOCK) s_cnt[i] = 0;
+    if (tid == 0) {
+        s_nl = 0;
+        s_flags = 0;
+        s_mf = 0;
+        s_xkey = 0;
+        for (int k = 0; k < 3; ++k) s_lc[k] = 0;
+        if (lead) *p.xsel = ~0ull;          // published by the first barrier
+    }
+    __syncthreads();
+
+    // append v to list l (one LDS atomic per wave); over capacity sets SF_OVER
+    auto append = [&](unsigned l, unsigned v) {
+        const unsigned long long am = __ballot(1);
+        const int ld = __ffsll((long long)am) - 1;
+        unsigned k0 = 0;
+        if ((int)lane == ld) k0 = atomicAdd(&s_nl, (unsigned)__popcll(am));
+        const unsigned k = __shfl(k0, ld) + (unsigned)__popcll(am & ((1ull << lane) - 1ull));
+        if (k < p.qcap) list[l][k] = v;
+        else atomicOr(&s_flags, SF_OVER);
+    };
+
+    // ---- Initialization (Algorithm 3) of this workgroup's chunk of vertices
+    {
+        const long long chunk = (nv + G - 1) / G;
+        const long long lo = (long long)r * chunk, hi = min(nv, lo + chunk);
+        unsigned mf = 0, bad = 0;
+        for (long long v = lo + tid; v < hi; v += BLOCK) {
+            const bool a = p.A[v] != 0, b = p.B[v] != 0;
+            if (a && b) bad |= 2;
+            for (long long j = p.off[v]; j < p.off[v + 1]; ++j) {
+                const unsigned x1 = p.f1[j], x2 = p.f2[j];
+                if (!x1 || !x2) bad |= 1;
+                mf = x1 > mf ? x1 : mf;
+            }
+            p.lab[v] = a ? p.M : 0u;
+            p.stamp[v] = 0xFFFFFFFFu;
+            if (a) append(0, (unsigned)v);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mf = max(mf, (unsigned)__shfl_xor(mf, o));
+            bad |= __shfl_xor(bad, o);
+        }
+        if (lane == 0) {
+            if (mf) atomicMax(&s_mf, mf);
+            if (bad & 1) atomicOr(&s_flags, SF_BAD);
+            if (bad & 2) atomicOr(&s_flags, SF_INVAL);
+        }
+    }
+    int status = ST_RUNNING;
+    unsigned W = 2;
+    {
+        Comb mine, all;
+        mine.mn = 0xFFFFFFFFu;
+        __syncthreads();
+        mine.orf = s_flags & (SF_BAD | SF_INVAL | SF_OVER);
+        mine.s0 = mine.s1 = mine.s2 = 0;
+        mine.mx = s_mf;
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, true)) status = ST_BROKEN;
+        else if (all.orf & (SF_BAD | SF_INVAL)) status = ST_INVAL;
+        else if (all.orf & SF_OVER) status = ST_OVERFLOW;
+        while (W <= (unsigned)all.mx) W <<= 1;
+    }
+    const unsigned Wm = W - 1;
+    const unsigned long long S = p.pool_flows / ((unsigned long long)G * W);
+    uint4 *wheel = p.pool + (unsigned long long)r * W * S;
+    unsigned cur = 0, nl = s_nl, F = 0, cyc = 0;
+    long long t = 0;
+    bool found = false;
+    unsigned X = 0, LX = 0;
+    __syncthreads();
+
+    while (status == ST_RUNNING) {
+        // ---- Departure (Steps 4-5) from this workgroup's part of I_t; its
+        // counts are committed unless the cycle turns out to be the last
+        unsigned long long dD = 0, dE = 0;
+        if (tid == 0) s_min = 0xFFFFFFFFu;
+        __syncthreads();
+        for (unsigned k = tid; k < nl; k += BLOCK) {
+            const unsigned Q = list[cur][k];
+            const unsigned L = p.lab[Q];
+            for (long long j = p.off[Q]; j < p.off[Q + 1]; ++j) {
+                ++dD;
+                const unsigned P = (unsigned)p.nbr[j];
+                const int q = (int)L - (int)p.f2[j];
+                if (q > 0 && (unsigned)q > p.lab[P]) {
+                    const unsigned bk = (unsigned)((t + p.f1[j]) & Wm);
+                    const unsigned pos = atomicAdd(&s_cnt[bk], 1u);
+                    if (pos < S) wheel[(unsigned long long)bk * S + pos] = make_uint4(P, (unsigned)q, Q, (unsigned)j);
+                    else atomicOr(&s_flags, SF_OVER);
+                    ++dE;
+                }
+            }
+        }
+        __syncthreads();
+        unsigned long long transit = 0;
+        {
+            unsigned best = 0xFFFFFFFFu;
+            for (unsigned bk = tid; bk < W; bk += BLOCK) {
+                const unsigned v = s_cnt[bk];
+                if (v) {
+                    best = min(best, (unsigned)((bk - (unsigned)t) & Wm));
+                    transit += v;
+                    if (v > S) atomicOr(&s_flags, SF_OVER);
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                best = min(best, (unsigned)__shfl_xor(best, o));
+                transit += __shfl_xor(transit, o);
+            }
+            if (tid == 0) s_red[0] = 0;
+            __syncthreads();
+            if (lane == 0) {
+                if (best != 0xFFFFFFFFu) atomicMin(&s_min, best);
+                if (transit) atomicAdd(&s_red[0], transit);
+            }
+            __syncthreads();
+            transit = s_red[0];
+        }
+        Comb mine, all;
+        mine.mn = s_min;
+        mine.orf = s_flags & (SF_OVER | SF_BHIT);
+        mine.s0 = F;
+        mine.s1 = nl;
+        mine.s2 = transit;
+        mine.mx = s_xkey;
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false)) { status = ST_BROKEN; break; }
+        if (all.orf & SF_OVER) { status = ST_OVERFLOW; break; }
+        if (lead && tid == 0) {
+            const unsigned long long a0 = all.rest ? ld64(&all.rest[0]) : all.s0;
+            const unsigned long long a1 = all.rest ? ld64(&all.rest[1]) : all.s1;
+            const unsigned long long a2 = all.rest ? ld64(&all.rest[2]) : all.s2;
+            cU += a1;
+            if (cyc > 0) {
+                s_lc[0] += a0 > 0 ? 1 : 0;
+                s_lc[2] = a1 > s_lc[2] ? a1 : s_lc[2];
+            }
+            // in transit after this sending round, unless the round is the last
+            if (!(all.orf & SF_BHIT)) s_lc[1] = a2 > s_lc[1] ? a2 : s_lc[1];
+        }
+        if (all.orf & SF_BHIT) {
+            // ---- Step 6 (Algorithm 2): T = t; x from the bucket delivered at t.
+            found = true;
+            X = (unsigned)(0xFFFFFFFFull - (all.mx & 0xFFFFFFFFull));
+            LX = (unsigned)(all.mx >> 32);
+            const uint4 *bkt = wheel + (unsigned long long)(t & Wm) * S;
+            for (unsigned k = tid; k < F; k += BLOCK) {
+                const uint4 f = bkt[k];
+                if (f.x == X && f.y == LX) atomicMin(p.xsel, ((unsigned long long)f.z << 32) | f.w);
+            }
+            status = ST_DONE;
+            break;
+        }
+        cD += dD;
+        cE += dE;
+        if (all.mn == 0xFFFFFFFFu) { status = ST_DONE; break; }            // condition 2
+        if (p.max_cycles > 0 && (long long)cyc >= p.max_cycles) { status = ST_CANCELED; break; }
+        t += all.mn;
+        ++cyc;
+
+        // ---- Arrival (Steps 1-3, 8): deliver this workgroup's bucket t
+        const unsigned bk = (unsigned)(t & Wm);
+        F = (unsigned)min((unsigned long long)s_cnt[bk], S);
+        const uint4 *bkt = wheel + (unsigned long long)bk * S;
+        if (tid == 0) {
+            s_nl = 0;
+            s_flags &= SF_OVER;
+            s_xkey = 0;
+        }
+        __syncthreads();
+        for (unsigned k = tid; k < F; k += BLOCK) {
+            const uint4 f = bkt[k];
+            const unsigned old = atomicMax(&p.lab[f.x], f.y);
+            if (f.y > old && atomicExch(&p.stamp[f.x], cyc) != cyc) append(cur ^ 1u, f.x);
+        }
+        cR += tid == 0 ? F : 0;
+        __syncthreads();
+        if (tid == 0) s_cnt[bk] = 0;
+        // every delivery of t lands before any departure reads a label
+        {
+            Comb m2, a2;
+            m2.mn = 0xFFFFFFFFu;
+            m2.orf = s_flags & SF_OVER;
+            m2.s0 = m2.s1 = m2.s2 = m2.mx = 0;
+            if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, m2, a2, false)) { status = ST_BROKEN; break; }
+            if (a2.orf & SF_OVER) { status = ST_OVERFLOW; break; }
+        }
+        cur ^= 1u;
+        nl = s_nl;
+        // vertices of B in the improved set: best (label, -index) with final labels
+        {
+            unsigned long long bestB = 0;
+            for (unsigned k = tid; k < nl; k += BLOCK) {
+                const unsigned v = list[cur][k];
+                if (p.B[v]) {
+                    const unsigned long long key = ((unsigned long long)p.lab[v] << 32) | (0xFFFFFFFFull - v);
+                    bestB = key > bestB ? key : bestB;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long ob = __shfl_xor(bestB, o);
+                bestB = ob > bestB ? ob : bestB;
+            }
+            if (lane == 0 && bestB) {
+                atomicMax(&s_xkey, bestB);
+                atomicOr(&s_flags, SF_BHIT);
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- outputs; the selection of x needs every workgroup's bucket scan
+    if (found) {
+        Comb m3, a3;
+        m3.mn = 0xFFFFFFFFu;
+        m3.orf = 0;
+        m3.s0 = m3.s1 = m3.s2 = m3.mx = 0;
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, m3, a3, false)) status = ST_BROKEN;
+    }
+    if (status == ST_DONE && p.labels_out) {
+        const long long chunk = (nv + G - 1) / G;
+        const long long lo = (long long)r * chunk, hi = min(nv, lo + chunk);
+        for (long long v = lo + tid; v < hi; v += BLOCK) p.labels_out[v] = p.lab[v];
+    }
+    __syncthreads();
+    if (tid == 0)
+        for (int i = 0; i < 4; ++i) s_red[i] = 0;
+    __syncthreads();
+    if (cD) atomicAdd(&s_red[1], cD);
+    if (cE) atomicAdd(&s_red[2], cE);
+    if (cR) atomicAdd(&s_red[3], cR);
+    __syncthreads();
+    if (tid == 0) {
+        Out *out = p.out;
+        if (s_red[1]) atomicAdd(&out->ctr[2], s_red[1]);
+        if (s_red[2]) atomicAdd(&out->ctr[3], s_red[2]);
+        if (s_red[3]) atomicAdd(&out->ctr[4], s_red[3]);
+        if (lead) {
+            out->ctr[0] = s_lc[0];
+            out->ctr[1] = cU;
+            out->ctr[5] = s_lc[1];
+            out->ctr[6] = s_lc[2];
+            const int br = __hip_atomic_load(&p.bar->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            out->status = br ? ST_BROKEN : status;
+            if (status == ST_DONE && found) {
+                const unsigned long long xs = __hip_atomic_load(p.xsel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned Y = (unsigned)(xs >> 32), j = (unsigned)xs;
+                if (xs == ~0ull || (long long)j >= p.m) {
+                    out->status = ST_BROKEN;
+                } else {
+                    out->res[0] = t;
+                    out->res[1] = X;
+                    out->res[2] = p.eid[j];
+                    out->res[3] = Y;
+                    out->res[4] = (long long)p.M - (long long)LX;
+                }
+            } else if (status == ST_DONE) {
+                for (int i = 0; i < 5; ++i) out->res[i] = -1;
+            }
+        }
+    }
+}
+
 // Clear the quit bit and the watcher flag before a serving launch.
 __global__ void k_serve_reset(unsigned long long *state, unsigned *watch)
 {
@@ -2164,6 +2479,12 @@ struct csp_ctx {
     unsigned long long wall_khz = 100000;
     unsigned *lab = nullptr;
     size_t lab_cap = 0;
+    // general graphs
+    unsigned *gstamp = nullptr, *glists = nullptr;
+    size_t gstamp_cap = 0, glists_cap = 0;
+    uint4 *gpool = nullptr;
+    size_t gpool_cap = 0;
+    unsigned long long gpool_seen = 0;
     uint8_t *rec = nullptr;
     size_t rec_cap = 0;
     unsigned *queue = nullptr;
@@ -2782,6 +3103,109 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
                   csp_result *out, csp_counters *cnt, int64_t max_cycles, void *stream)
 {
     return solve_impl(ctx, d, n, f1, f2, A, B, M, labels, out, cnt, max_cycles, stream, false);
+}
+
+int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int32_t *nbr, const uint8_t *f1,
+                        const uint8_t *f2, const int64_t *eid, const uint8_t *A, const uint8_t *B, uint32_t M,
+                        uint32_t *labels, csp_result *out, csp_counters *cnt, int64_t max_cycles, void *stream)
+{
+    if (!ctx || !out || !off || !nbr || !f1 || !f2 || !eid || !A || !B) return fail(ctx, CSP_EINVAL, "null argument");
+    if (nv < 1 || nv >= (1ll << 31)) return fail(ctx, CSP_EINVAL, "vertex count out of range");
+    if (M < 1 || M > CSP_MAX_M) return fail(ctx, CSP_EINVAL, "M out of range");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    long long m = 0;
+    HIP_TRY(hipMemcpyAsync(&m, off + nv, sizeof(m), hipMemcpyDeviceToHost, s), "edge count");
+    HIP_TRY(hipStreamSynchronize(s), "edge count");
+    if (m < 0 || m >= (1ll << 31)) return fail(ctx, CSP_EINVAL, "adjacency entries out of range");
+    const void *kf = (const void *)k_graph;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kf, BLOCK, 0) != hipSuccess || nb < 1)
+        return fail(ctx, CSP_EDEVICE, "graph kernel occupancy");
+    const long long gmax = std::min<long long>(GMAX, (long long)nb * ctx->num_cu);
+    long long G = ctx->blocks_override > 0 ? ctx->blocks_override : (nv + 8191) / 8192;
+    if (nv <= 32768 && ctx->blocks_override <= 0) G = 1;
+    G = std::max(1ll, std::min(G, gmax));
+    int rc = grow(ctx, &ctx->lab, ctx->lab_cap, (size_t)nv, "labels");
+    if (!rc) rc = grow(ctx, &ctx->gstamp, ctx->gstamp_cap, (size_t)nv, "graph stamps");
+    if (rc) return rc;
+    unsigned long long qcap = std::min<unsigned long long>((unsigned long long)nv,
+                                                           std::max<unsigned long long>(4096, 2ull * nv / G));
+    unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G
+                                             : std::max<unsigned long long>({1ull << 20, 8ull * (unsigned long long)m,
+                                                                             ctx->gpool_seen});
+    const unsigned long long pool_max = 256ull * G * ((unsigned long long)m + 1) + (1ull << 20);
+    for (;;) {
+        rc = grow(ctx, &ctx->glists, ctx->glists_cap, (size_t)(2ull * G * qcap), "graph frontier lists");
+        if (!rc) rc = grow(ctx, &ctx->gpool, ctx->gpool_cap, (size_t)pool, "graph transit pool");
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(BLOCK), 0, s, ctx->ctl);
+        GJ p;
+        memset(&p, 0, sizeof(p));
+        p.nv = nv;
+        p.m = m;
+        p.off = reinterpret_cast<const long long *>(off);
+        p.nbr = nbr;
+        p.f1 = f1;
+        p.f2 = f2;
+        p.eid = reinterpret_cast<const long long *>(eid);
+        p.A = A;
+        p.B = B;
+        p.M = M;
+        p.lab = ctx->lab;
+        p.stamp = ctx->gstamp;
+        p.lists = ctx->glists;
+        p.qcap = qcap;
+        p.pool = ctx->gpool;
+        p.pool_flows = pool;
+        p.bar = &ctx->ctl->rbar;
+        p.out = &ctx->ctl->rout;
+        p.xsel = &ctx->ctl->xkey;
+        p.labels_out = labels;
+        p.max_cycles = max_cycles;
+        p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+        void *args[] = {&p};
+        HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
+        HIP_TRY(hipLaunchCooperativeKernel(kf, dim3((unsigned)G), dim3(BLOCK), args, 0, s), "graph launch");
+        HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
+        {
+            const size_t lo = offsetof(Ctl, xkey), hi = offsetof(Ctl, rbar);
+            HIP_TRY(hipMemcpyAsync(reinterpret_cast<uint8_t *>(ctx->h_ctl) + lo,
+                                   reinterpret_cast<const uint8_t *>(ctx->ctl) + lo, hi - lo, hipMemcpyDeviceToHost, s),
+                    "ctl copy");
+        }
+        HIP_TRY(hipStreamSynchronize(s), "graph solve");
+        const Out &o = ctx->h_ctl->rout;
+        if (o.status == ST_INVAL) return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0, or A and B overlap");
+        if (o.status == ST_OVERFLOW) {
+            if (pool >= pool_max && qcap >= (unsigned long long)nv)
+                return fail(ctx, CSP_EOVERFLOW, "graph transit pool overflow at the edge bound");
+            pool = std::min(pool * 2, pool_max);
+            qcap = std::min<unsigned long long>(qcap * 2, (unsigned long long)nv);
+            continue;
+        }
+        if (o.status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
+        if (o.status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out or inconsistent result");
+        if (o.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "graph solve did not finish");
+        if (!ctx->pool_hint) ctx->gpool_seen = std::max(ctx->gpool_seen, pool);
+        HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
+        ctx->last_path = 2;
+        out->T = o.res[0];
+        out->X = o.res[1];
+        out->x = o.res[2];
+        out->Y = o.res[3];
+        out->F2 = o.res[4];
+        if (cnt) {
+            cnt->C = (int64_t)o.ctr[0];
+            cnt->U = (int64_t)o.ctr[1];
+            cnt->D = (int64_t)o.ctr[2];
+            cnt->E = (int64_t)o.ctr[3];
+            cnt->R = (int64_t)o.ctr[4];
+            cnt->P = (int64_t)o.ctr[5];
+            cnt->I = (int64_t)o.ctr[6];
+        }
+        return CSP_OK;
+    }
 }
 
 int csp_reconstruct_log_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2,

@@ -337,3 +337,62 @@ def face_mask_torch(d: int, n: int, axis: int, coord: int, device="cuda"):
     idx[d - 1 - axis] = coord
     m[tuple(idx)] = 1
     return m.reshape(-1)
+
+
+# ----------------------------------------------------------------------------
+# general graphs (adjacency lists)
+# ----------------------------------------------------------------------------
+
+def graph_csr(nv: int, us, vs, f1, f2, ids=None):
+    """Adjacency arrays of an undirected graph from its edge list: both
+    directions of every edge, neighbours of each vertex in ascending order
+    (ties by edge id), edge id = position in the list unless given.
+    Returns off int64 [nv+1], nbr int32, f1 uint8, f2 uint8, eid int64."""
+    us = np.asarray(us, dtype=np.int64)
+    vs = np.asarray(vs, dtype=np.int64)
+    f1 = np.asarray(f1, dtype=np.uint8)
+    f2 = np.asarray(f2, dtype=np.uint8)
+    ids = np.arange(us.size, dtype=np.int64) if ids is None else np.asarray(ids, dtype=np.int64)
+    src = np.concatenate([us, vs])
+    dst = np.concatenate([vs, us])
+    a1 = np.concatenate([f1, f1])
+    a2 = np.concatenate([f2, f2])
+    e = np.concatenate([ids, ids])
+    order = np.lexsort((e, dst, src))
+    src, dst, a1, a2, e = src[order], dst[order], a1[order], a2[order], e[order]
+    off = np.zeros(nv + 1, dtype=np.int64)
+    np.add.at(off, src + 1, 1)
+    off = np.cumsum(off)
+    return off, dst.astype(np.int32), a1, a2, e
+
+
+def random_graph(nv: int, seed: int, K1: int, K2: int, max_deg: int = 6, chords: int = 2):
+    """A connected bounded-degree graph: a path 0-1-...-(nv-1) plus `chords`
+    random chords per vertex (skipped when they would exceed max_deg or
+    repeat an edge).  f1, f2 i.i.d. uniform on 1..K from the same streams as
+    the lattices.  Returns (us, vs, f1, f2) as arrays."""
+    z = stream(mix64(seed ^ 0xC0), nv * chords)
+    deg = np.zeros(nv, dtype=np.int64)
+    seen = set()
+    us, vs = [], []
+    for u in range(nv - 1):
+        us.append(u)
+        vs.append(u + 1)
+        seen.add((u, u + 1))
+        deg[u] += 1
+        deg[u + 1] += 1
+    for k in range(nv * chords):
+        u = k // chords
+        v = int(z[k] % np.uint64(nv))
+        a, b = min(u, v), max(u, v)
+        if a == b or (a, b) in seen or deg[a] >= max_deg or deg[b] >= max_deg:
+            continue
+        seen.add((a, b))
+        us.append(a)
+        vs.append(b)
+        deg[a] += 1
+        deg[b] += 1
+    m = len(us)
+    f1 = uniform_int(stream(mix64(seed ^ 0xF1), m), K1).astype(np.uint8)
+    f2 = uniform_int(stream(mix64(seed ^ 0xF2), m), K2).astype(np.uint8)
+    return np.array(us, dtype=np.int64), np.array(vs, dtype=np.int64), f1, f2

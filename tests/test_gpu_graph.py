@@ -1,0 +1,136 @@
+"""General bounded-degree graphs on the GPU (adjacency lists): T, X, x, Y,
+F2, every label and every counter equal the oracle's graph solve; the
+section-3 worked example; a lattice given as a graph equals the lattice
+solve."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1511_06441_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def solver(torch):
+    from paper_1511_06441_amd import csp
+    s = csp.Solver(0)
+    yield s
+    s.close()
+
+
+def _gpu(solver, torch, nv, edges, A, B, M, blocks=0):
+    from paper_1511_06441_amd import csp
+    us, vs, f1, f2 = edges[:4]
+    ids = edges[4] if len(edges) > 4 else None
+    g = csp.graph_to_device(gen.graph_csr(nv, us, vs, f1, f2, ids))
+    At = torch.from_numpy(A).cuda()
+    Bt = torch.from_numpy(B).cuda()
+    lab = torch.zeros(nv, dtype=torch.int32, device="cuda")
+    csp.csp_set_blocks(solver.ctx, blocks)
+    try:
+        res, cnt = csp.csp_solve_graph_dev(solver.ctx, g, At, Bt, M, labels=lab)
+    finally:
+        csp.csp_set_blocks(solver.ctx, 0)
+    torch.cuda.synchronize()
+    return res, cnt, lab.cpu().numpy().view(np.uint32)
+
+
+def _oracle(nv, edges, A, B, M):
+    from oracle import oracle as O
+    us, vs, f1, f2 = edges[:4]
+    graph = O.graph_from_edges(nv, [(int(a), int(b), int(c), int(d)) for a, b, c, d in zip(us, vs, f1, f2)])
+    return O.solve_graph(graph, A, B, M)
+
+
+def _sets(nv, seed, na, nb):
+    z = gen.stream(gen.mix64(seed ^ 0xAB), na + nb) % np.uint64(nv)
+    A = np.zeros(nv, np.uint8)
+    B = np.zeros(nv, np.uint8)
+    A[z[:na].astype(np.int64)] = 1
+    for v in z[na:].astype(np.int64):
+        if not A[v]:
+            B[v] = 1
+    return A, B
+
+
+def test_worked_example(solver, torch):
+    with open(os.path.join(GOLDEN, "worked_example.json")) as fh:
+        ex = json.load(fh)
+    nv = ex["vertices"] + 1                                   # vertex 0 unused
+    e = np.array(ex["edges"], dtype=np.int64)
+    edges = (e[:, 0], e[:, 1], e[:, 2], e[:, 3])
+    A = np.zeros(nv, np.uint8)
+    A[ex["A"]] = 1
+    B = np.zeros(nv, np.uint8)
+    B[ex["B"]] = 1
+    res, cnt, lab = _gpu(solver, torch, nv, edges, A, B, ex["M"])
+    ref = _oracle(nv, edges, A, B, ex["M"])
+    assert (res.T, res.F2, res.X) == (ex["T"], ex["F2"], ex["B"][0])
+    assert res.tuple() == ref.tuple()
+    assert cnt.asdict() == ref.counters
+    assert np.array_equal(lab, ref.labels)
+    assert res.Y == ex["recovered_path"][-2]
+
+
+GRAPHS = [(60, 1, 9, 9, 2, 3, 80), (1000, 2, 20, 20, 5, 5, 400), (5000, 3, 5, 30, 8, 8, 900),
+          (20000, 4, 50, 50, 20, 10, 4000), (20000, 5, 10, 10, 3, 3, 90), (120000, 6, 30, 30, 40, 20, 9000)]
+
+
+@pytest.mark.parametrize("case", GRAPHS)
+@pytest.mark.parametrize("blocks", [0, 8])
+def test_random_graph_vs_oracle(solver, torch, case, blocks):
+    nv, seed, K1, K2, na, nb, M = case
+    edges = gen.random_graph(nv, seed, K1, K2)
+    A, B = _sets(nv, seed, na, nb)
+    _say("graph", nv, "seed", seed, "M", M, "blocks", blocks)
+    res, cnt, lab = _gpu(solver, torch, nv, edges, A, B, M, blocks)
+    ref = _oracle(nv, edges, A, B, M)
+    assert res.tuple() == ref.tuple()
+    assert cnt.asdict() == ref.counters
+    assert np.array_equal(lab, ref.labels)
+
+
+@pytest.mark.parametrize("d,n,seed,K,M,blocks", [(2, 64, 1, 5, 200, 0), (3, 20, 4, 12, 300, 4), (2, 200, 9, 9, 1200, 16)])
+def test_lattice_as_graph_equals_lattice_solve(solver, torch, d, n, seed, K, M, blocks):
+    from paper_1511_06441_amd import csp
+    from tests import pins
+    inst = gen.opposite_faces(d, n, seed, K, K, M)
+    edges = pins.lattice_edge_list(d, n, inst.f1, inst.f2)          # (u, v, f1, f2, lattice edge id)
+    res, cnt, lab = _gpu(solver, torch, inst.N, edges, inst.A, inst.B, M, blocks)
+    di = csp.to_device(inst)
+    lab2 = torch.zeros(inst.N, dtype=torch.int32, device="cuda")
+    r2, c2 = solver.solve(di, labels=lab2)
+    assert res.tuple() == r2.tuple()
+    assert cnt.asdict() == c2.asdict()
+    assert np.array_equal(lab, lab2.cpu().numpy().view(np.uint32))
+
+
+def test_graph_invalid_inputs(solver, torch):
+    from paper_1511_06441_amd import csp
+    edges = gen.random_graph(50, 7, 5, 5)
+    A, B = _sets(50, 7, 2, 2)
+    bad = (edges[0], edges[1], edges[2].copy(), edges[3])
+    bad[2][3] = 0
+    with pytest.raises(csp.CspError):
+        _gpu(solver, torch, 50, bad, A, B, 40)
+    A2 = A.copy()
+    A2[np.argmax(B)] = 1
+    with pytest.raises(csp.CspError):
+        _gpu(solver, torch, 50, edges, A2, B, 40)
