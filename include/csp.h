@@ -208,7 +208,9 @@ int csp_last_trace_rows(const csp_ctx *ctx, int64_t *rows);
  * accumulates wall-clock time per phase; csp_last_phase_us fills us[6] with
  * microseconds spent in: departure work, the barrier after it, finding the
  * next time, arrival work, the barrier after it, and the frontier gather,
- * for the last successful solve. */
+ * for the last successful solve.  The general-graph solve fills the same
+ * slots (finding the next time is part of its barrier, so that slot is 0;
+ * the last slot is the listing of each chunk's improved vertices). */
 int csp_set_phase_timing(csp_ctx *ctx, int on);
 int csp_last_phase_us(const csp_ctx *ctx, double *us);
 

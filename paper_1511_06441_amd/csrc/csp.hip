@@ -2137,10 +2137,13 @@ __global__ void __launch_bounds__(BLOCK) k_serve(ServeArgs a)
 // arithmetic: off[v] .. off[v+1] index nbr, f1, f2 and the edge id of each
 // directed entry (both directions of every edge present).  Labels live in
 // HBM and are raised with atomicMax; each workgroup files the flows it sends
-// in its own wheel segment and keeps the list of vertices it improved.  A
-// flow is (destination, quality, sender, adjacency entry), so the last edge
-// x and its sender Y come out of the bucket delivered at T.  Per cycle: an
-// arrival phase, a barrier (so departures read every delivery of t), the
+// in its own wheel segment.  A delivery that raises a label stamps the
+// vertex with the cycle; after the barrier each workgroup lists the stamped
+// vertices of its own contiguous chunk, so departures follow the static
+// partition whichever workgroup delivered.  A flow is (destination,
+// quality, sender, adjacency entry), so the last edge x and its sender Y
+// come out of the bucket delivered at T.  Per cycle: an arrival phase, a
+// barrier (so departures read every delivery of t), the listing of I_t, the
 // departure phase, and a combining barrier that returns the next time, the
 // best B key and the counts.
 // ---------------------------------------------------------------------------
@@ -2154,8 +2157,8 @@ struct GJ {
     const uint8_t *A, *B;
     unsigned M;
     unsigned *lab;                 // [nv]
-    unsigned *stamp;               // [nv] cycle in which the vertex last joined an improved set
-    unsigned *lists;               // [2][G][qcap]
+    unsigned *stamp;               // [nv] last cycle in which a delivery raised the label
+    unsigned *lists;               // [G][qcap] I_t of each workgroup's chunk of vertices
     unsigned long long qcap;
     uint4 *pool;                   // [G][W][S] flows (dst, q, sender, adjacency entry)
     unsigned long long pool_flows;
@@ -2165,6 +2168,7 @@ struct GJ {
     unsigned *labels_out;
     long long max_cycles;
     unsigned long long wait_limit;
+    int prof;                      // accumulate phase times in workgroup 0
 };
 
 __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
@@ -2179,8 +2183,9 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
     const bool lead = r == 0;
     const long long nv = p.nv;
     unsigned epoch = 0;
-    unsigned *list[2] = {p.lists + (unsigned long long)r * p.qcap,
-                         p.lists + ((unsigned long long)G + r) * p.qcap};
+    unsigned *const list = p.lists + (unsigned long long)r * p.qcap;
+    const long long c_chunk = (nv + G - 1) / G;
+    const long long c_lo = min(nv, (long long)r * c_chunk), c_hi = min(nv, c_lo + c_chunk);
     unsigned long long cU = 0, cD = 0, cE = 0, cR = 0;
 
     for (unsigned i = tid; i < MAXW; i += BLOCK) s_cnt[i] = 0;
@@ -2194,14 +2199,15 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
     }
     __syncthreads();
 
-    // append v to list l (one LDS atomic per wave); over capacity sets SF_OVER
-    auto append = [&](unsigned l, unsigned v) {
+    // append v to this workgroup's list (one LDS atomic per wave); over
+    // capacity sets SF_OVER
+    auto append = [&](unsigned v) {
         const unsigned long long am = __ballot(1);
         const int ld = __ffsll((long long)am) - 1;
         unsigned k0 = 0;
         if ((int)lane == ld) k0 = atomicAdd(&s_nl, (unsigned)__popcll(am));
         const unsigned k = __shfl(k0, ld) + (unsigned)__popcll(am & ((1ull << lane) - 1ull));
-        if (k < p.qcap) list[l][k] = v;
+        if (k < p.qcap) list[k] = v;
         else atomicOr(&s_flags, SF_OVER);
     };
 
@@ -2220,7 +2226,7 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
             }
             p.lab[v] = a ? p.M : 0u;
             p.stamp[v] = 0xFFFFFFFFu;
-            if (a) append(0, (unsigned)v);
+            if (a) append((unsigned)v);
         }
         for (int o = 32; o > 0; o >>= 1) {
             mf = max(mf, (unsigned)__shfl_xor(mf, o));
@@ -2249,10 +2255,21 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
     const unsigned Wm = W - 1;
     const unsigned long long S = p.pool_flows / ((unsigned long long)G * W);
     uint4 *wheel = p.pool + (unsigned long long)r * W * S;
-    unsigned cur = 0, nl = s_nl, F = 0, cyc = 0;
+    unsigned nl = s_nl, F = 0, cyc = 0;
     long long t = 0;
     bool found = false;
     unsigned X = 0, LX = 0;
+    unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
+    const bool timing = p.prof && lead && tid == 0;
+#define GPHASE(k)                                            \
+    do {                                                     \
+        if (timing) {                                        \
+            const unsigned long long now_ = wall_clock64();  \
+            ph[k] += now_ - ph_t;                            \
+            ph_t = now_;                                     \
+        }                                                    \
+    } while (0)
+    if (timing) ph_t = wall_clock64();
     __syncthreads();
 
     while (status == ST_RUNNING) {
@@ -2262,22 +2279,43 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
         if (tid == 0) s_min = 0xFFFFFFFFu;
         __syncthreads();
         for (unsigned k = tid; k < nl; k += BLOCK) {
-            const unsigned Q = list[cur][k];
+            const unsigned Q = list[k];
             const unsigned L = p.lab[Q];
-            for (long long j = p.off[Q]; j < p.off[Q + 1]; ++j) {
-                ++dD;
-                const unsigned P = (unsigned)p.nbr[j];
-                const int q = (int)L - (int)p.f2[j];
-                if (q > 0 && (unsigned)q > p.lab[P]) {
-                    const unsigned bk = (unsigned)((t + p.f1[j]) & Wm);
-                    const unsigned pos = atomicAdd(&s_cnt[bk], 1u);
-                    if (pos < S) wheel[(unsigned long long)bk * S + pos] = make_uint4(P, (unsigned)q, Q, (unsigned)j);
-                    else atomicOr(&s_flags, SF_OVER);
-                    ++dE;
+            const long long j0 = p.off[Q], j1 = p.off[Q + 1];
+            // neighbours in groups of GU: their entries, then their labels, are
+            // loaded together, so a group costs two memory round trips
+            constexpr int GU = 4;
+            for (long long jb = j0; jb < j1; jb += GU) {
+                unsigned P[GU], a1[GU], a2[GU], lp[GU];
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const long long j = jb + u;
+                    P[u] = j < j1 ? (unsigned)p.nbr[j] : 0u;
+                    a1[u] = j < j1 ? (unsigned)p.f1[j] : 0u;
+                    a2[u] = j < j1 ? (unsigned)p.f2[j] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < GU; ++u) lp[u] = jb + u < j1 ? p.lab[P[u]] : 0xFFFFFFFFu;
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const long long j = jb + u;
+                    if (j >= j1) continue;
+                    ++dD;
+                    const int q = (int)L - (int)a2[u];
+                    if (q > 0 && (unsigned)q > lp[u]) {
+                        const unsigned bk = (unsigned)((t + a1[u]) & Wm);
+                        const unsigned pos = atomicAdd(&s_cnt[bk], 1u);
+                        if (pos < S)
+                            wheel[(unsigned long long)bk * S + pos] = make_uint4(P[u], (unsigned)q, Q, (unsigned)j);
+                        else
+                            atomicOr(&s_flags, SF_OVER);
+                        ++dE;
+                    }
                 }
             }
         }
         __syncthreads();
+        GPHASE(0);
         unsigned long long transit = 0;
         {
             unsigned best = 0xFFFFFFFFu;
@@ -2310,6 +2348,7 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
         mine.s2 = transit;
         mine.mx = s_xkey;
         if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false)) { status = ST_BROKEN; break; }
+        GPHASE(1);
         if (all.orf & SF_OVER) { status = ST_OVERFLOW; break; }
         if (lead && tid == 0) {
             const unsigned long long a0 = all.rest ? ld64(&all.rest[0]) : all.s0;
@@ -2353,13 +2392,22 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
             s_xkey = 0;
         }
         __syncthreads();
-        for (unsigned k = tid; k < F; k += BLOCK) {
-            const uint4 f = bkt[k];
-            const unsigned old = atomicMax(&p.lab[f.x], f.y);
-            if (f.y > old && atomicExch(&p.stamp[f.x], cyc) != cyc) append(cur ^ 1u, f.x);
+        for (unsigned k0 = tid; k0 < F; k0 += 4 * BLOCK) {
+            uint4 f[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k0 + u * BLOCK < F) f[u] = bkt[k0 + u * BLOCK];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k0 + u * BLOCK >= F) continue;
+                if (f[u].y <= p.lab[f[u].x]) continue;          // cannot raise the label
+                const unsigned old = atomicMax(&p.lab[f[u].x], f[u].y);
+                if (f[u].y > old) p.stamp[f[u].x] = cyc;        // joins I_t; its owner lists it
+            }
         }
         cR += tid == 0 ? F : 0;
         __syncthreads();
+        GPHASE(3);
         if (tid == 0) s_cnt[bk] = 0;
         // every delivery of t lands before any departure reads a label
         {
@@ -2370,16 +2418,26 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
             if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, m2, a2, false)) { status = ST_BROKEN; break; }
             if (a2.orf & SF_OVER) { status = ST_OVERFLOW; break; }
         }
-        cur ^= 1u;
-        nl = s_nl;
-        // vertices of B in the improved set: best (label, -index) with final labels
+        GPHASE(4);
+        // I_t of this workgroup's vertices: those stamped with this cycle, listed
+        // by their owner so the departures follow the static partition; with it,
+        // the vertices of B among them: best (label, -index) with final labels
         {
             unsigned long long bestB = 0;
-            for (unsigned k = tid; k < nl; k += BLOCK) {
-                const unsigned v = list[cur][k];
-                if (p.B[v]) {
-                    const unsigned long long key = ((unsigned long long)p.lab[v] << 32) | (0xFFFFFFFFull - v);
-                    bestB = key > bestB ? key : bestB;
+            for (long long v0 = c_lo + tid; v0 < c_hi; v0 += 4 * BLOCK) {
+                unsigned st[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) st[u] = v0 + u * BLOCK < c_hi ? p.stamp[v0 + u * BLOCK] : 0xFFFFFFFFu;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const long long v = v0 + u * BLOCK;
+                    if (__ballot(st[u] == cyc) == 0) continue;      // wave-uniform skip
+                    if (st[u] != cyc) continue;
+                    append((unsigned)v);
+                    if (p.B[v]) {
+                        const unsigned long long key = ((unsigned long long)p.lab[v] << 32) | (0xFFFFFFFFull - v);
+                        bestB = key > bestB ? key : bestB;
+                    }
                 }
             }
             for (int o = 32; o > 0; o >>= 1) {
@@ -2391,8 +2449,11 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
                 atomicOr(&s_flags, SF_BHIT);
             }
             __syncthreads();
+            nl = s_nl;
         }
+        GPHASE(5);
     }
+#undef GPHASE
 
     // ---- outputs; the selection of x needs every workgroup's bucket scan
     if (found) {
@@ -2421,6 +2482,7 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
         if (s_red[2]) atomicAdd(&out->ctr[3], s_red[2]);
         if (s_red[3]) atomicAdd(&out->ctr[4], s_red[3]);
         if (lead) {
+            for (int i = 0; i < 6; ++i) out->prof[i] = ph[i];
             out->ctr[0] = s_lc[0];
             out->ctr[1] = cU;
             out->ctr[5] = s_lc[1];
@@ -3129,14 +3191,14 @@ int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int3
     int rc = grow(ctx, &ctx->lab, ctx->lab_cap, (size_t)nv, "labels");
     if (!rc) rc = grow(ctx, &ctx->gstamp, ctx->gstamp_cap, (size_t)nv, "graph stamps");
     if (rc) return rc;
-    unsigned long long qcap = std::min<unsigned long long>((unsigned long long)nv,
-                                                           std::max<unsigned long long>(4096, 2ull * nv / G));
+    // each workgroup lists only its own chunk of vertices
+    unsigned long long qcap = (unsigned long long)((nv + G - 1) / G);
     unsigned long long pool = ctx->pool_hint ? ctx->pool_hint * 256ull * G
                                              : std::max<unsigned long long>({1ull << 20, 8ull * (unsigned long long)m,
                                                                              ctx->gpool_seen});
     const unsigned long long pool_max = 256ull * G * ((unsigned long long)m + 1) + (1ull << 20);
     for (;;) {
-        rc = grow(ctx, &ctx->glists, ctx->glists_cap, (size_t)(2ull * G * qcap), "graph frontier lists");
+        rc = grow(ctx, &ctx->glists, ctx->glists_cap, (size_t)(G * qcap), "graph frontier lists");
         if (!rc) rc = grow(ctx, &ctx->gpool, ctx->gpool_cap, (size_t)pool, "graph transit pool");
         if (rc) return rc;
         hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(BLOCK), 0, s, ctx->ctl);
@@ -3164,6 +3226,7 @@ int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int3
         p.labels_out = labels;
         p.max_cycles = max_cycles;
         p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+        p.prof = ctx->prof;
         void *args[] = {&p};
         HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
         HIP_TRY(hipLaunchCooperativeKernel(kf, dim3((unsigned)G), dim3(BLOCK), args, 0, s), "graph launch");
@@ -3178,10 +3241,9 @@ int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int3
         const Out &o = ctx->h_ctl->rout;
         if (o.status == ST_INVAL) return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0, or A and B overlap");
         if (o.status == ST_OVERFLOW) {
-            if (pool >= pool_max && qcap >= (unsigned long long)nv)
+            if (pool >= pool_max)
                 return fail(ctx, CSP_EOVERFLOW, "graph transit pool overflow at the edge bound");
             pool = std::min(pool * 2, pool_max);
-            qcap = std::min<unsigned long long>(qcap * 2, (unsigned long long)nv);
             continue;
         }
         if (o.status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
@@ -3189,6 +3251,7 @@ int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int3
         if (o.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "graph solve did not finish");
         if (!ctx->pool_hint) ctx->gpool_seen = std::max(ctx->gpool_seen, pool);
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
+        for (int i = 0; i < 8; ++i) ctx->last_prof[i] = o.prof[i];
         ctx->last_path = 2;
         out->T = o.res[0];
         out->X = o.res[1];
