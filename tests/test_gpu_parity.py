@@ -157,6 +157,23 @@ def test_corner_and_boundary_shapes(solver, torch):
         _compare(inst, res, cnt, lab, ref)
 
 
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("case", [(2, 17, 31, 1), (2, 17, 32, 65535), (2, 17, 33, 65536), (3, 7, 34, 70001),
+                                  (2, 17, 35, 0x0FFFFFFF), (3, 9, 36, 0x0FFFFFFF), (4, 4, 37, 0x0FFFFFFF)],
+                         ids=lambda c: f"d{c[0]}n{c[1]}M{c[3]}")
+def test_extreme_M(solver, torch, case, path):
+    """M = 1 (no flow can leave A), M on both sides of the 16-bit label
+    boundary, and the largest M the library takes."""
+    d, n, seed, M = case
+    inst = gen.opposite_faces(d, n, seed, 9, 9, M)
+    _say("case", inst.name, "M", M, "path", path)
+    ref = _oracle(inst)
+    res, cnt, lab = gpu_solve(solver, torch, inst, path=path)
+    _compare(inst, res, cnt, lab, ref)
+    if M == 1:
+        assert res.T == -1
+
+
 def test_empty_A(solver, torch):
     inst = gen.square64(1)
     inst.A = np.zeros(inst.N, np.uint8)
