@@ -192,6 +192,22 @@ int csp_set_blocks(csp_ctx *ctx, int blocks);
 int csp_set_path(csp_ctx *ctx, int path);
 int csp_last_path(const csp_ctx *ctx);
 
+/* Autotuning of the single-solve kernel for one lattice shape.  Solves the
+ * problem (arguments as csp_solve_dev) twice per candidate configuration:
+ * workgroup counts of 1/4, 1/2, 1 and 2 times the automatic choice, and for
+ * d = 3 both range shapes (csp_set_path 0 and 3).  Every configuration must
+ * give the same result and counters (else CSP_EDEVICE).  The fastest, by
+ * kernel time (the automatic configuration unless another is at least 3 %
+ * faster), is recorded on ctx and used by later csp_solve_dev,
+ * csp_solve and reconstruction calls whose lattice has the same d and n^d,
+ * unless csp_set_blocks or csp_set_path set an override.  blocks, path and
+ * ms (nullable) receive the choice and its kernel time in milliseconds.
+ * Tuning changes speed only, never results.  csp_autotune_clear drops every
+ * recorded choice. */
+int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2, const uint8_t *A,
+                 const uint8_t *B, uint32_t M, int *blocks, int *path, float *ms, void *stream);
+int csp_autotune_clear(csp_ctx *ctx);
+
 /* Cycle trace for later csp_solve_dev calls on ctx (off when cap = 0):
  * trace is a device buffer of cap rows of four int64, one row per time at
  * which water is delivered (section 4, Algorithm 1's loop): t, flows

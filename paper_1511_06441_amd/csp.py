@@ -28,7 +28,7 @@ EXPORTED = (
     "csp_set_blocks", "csp_set_phase_timing", "csp_last_phase_us", "csp_set_path",
     "csp_last_path", "csp_solve_batch", "csp_serve_open", "csp_serve_submit",
     "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
-    "csp_reconstruct_log_dev", "csp_solve_graph_dev",
+    "csp_reconstruct_log_dev", "csp_solve_graph_dev", "csp_autotune", "csp_autotune_clear",
 )
 
 
@@ -97,6 +97,11 @@ def _load():
     lib.csp_set_path.restype = i32
     lib.csp_last_path.argtypes = [p]
     lib.csp_last_path.restype = i32
+    lib.csp_autotune.argtypes = [p, i32, i64, p, p, p, p, u32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                 ctypes.POINTER(ctypes.c_float), p]
+    lib.csp_autotune.restype = i32
+    lib.csp_autotune_clear.argtypes = [p]
+    lib.csp_autotune_clear.restype = i32
     lib.csp_set_phase_timing.argtypes = [p, i32]
     lib.csp_set_phase_timing.restype = i32
     lib.csp_last_phase_us.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
@@ -239,6 +244,19 @@ def csp_last_path(ctx) -> int:
     return lib.csp_last_path(ctx)
 
 
+def csp_autotune(ctx, d, n, f1, f2, A, B, M, stream=None):
+    """Time the candidate configurations for this lattice shape and record
+    the fastest on ctx; returns (blocks, path, kernel ms)."""
+    b, pth, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    _check(ctx, lib.csp_autotune(ctx, d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), M, ctypes.byref(b),
+                                 ctypes.byref(pth), ctypes.byref(ms), _stream(stream)))
+    return b.value, pth.value, ms.value
+
+
+def csp_autotune_clear(ctx):
+    _check(ctx, lib.csp_autotune_clear(ctx))
+
+
 PHASES = ("departure", "barrier_after_departure", "next_time", "arrival",
           "barrier_after_arrival", "frontier_gather")
 
@@ -356,6 +374,9 @@ class Solver:
         return csp_solve_dev(self.ctx, di.d, di.n, di.f1, di.f2, di.A, di.B,
                              di.M if M is None else M, labels=labels,
                              max_cycles=max_cycles, stream=stream)
+
+    def autotune(self, di: DeviceInstance, stream=None):
+        return csp_autotune(self.ctx, di.d, di.n, di.f1, di.f2, di.A, di.B, di.M, stream=stream)
 
     def reconstruct_log(self, di: DeviceInstance, cap=None, stream=None):
         cap = cap if cap is not None else min(di.M, di.N) + 1

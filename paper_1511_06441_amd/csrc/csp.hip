@@ -2565,6 +2565,14 @@ struct csp_ctx {
     unsigned long long pool_hint = 0;
     int blocks_override = 0;
     int path_override = 0;          // 0 auto, 1 LDS ranges, 2 global labels, 3 LDS pencils
+    // autotuned (blocks, path) per lattice shape, used when no override is set
+    struct Tuned {
+        int d;
+        long long N;
+        int blocks, path;
+        float ms;
+    };
+    std::vector<Tuned> tuned;
     long long *trace = nullptr;     // device [trace_cap][4], or null
     long long trace_cap = 0;
     long long last_trace_rows = 0;
@@ -2689,7 +2697,7 @@ size_t lds_bytes_for(long long c, int K, int lt)
     return (size_t)(4 * (lab_words + 2 * cw + MAXW));
 }
 
-LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M, int G_want);
+LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M, int G_want, int path);
 
 const void *solve_kernel(int d)
 {
@@ -2716,9 +2724,25 @@ int check_shape(csp_ctx *ctx, int d, int64_t n, uint32_t M, long long &N)
     return CSP_OK;
 }
 
+const csp_ctx::Tuned *tuned_for(const csp_ctx *ctx, int d, long long N)
+{
+    for (const auto &e : ctx->tuned)
+        if (e.d == d && e.N == N) return &e;
+    return nullptr;
+}
+
+// Kernel choice of a solve: the override, else the autotuned one, else automatic.
+int path_for(const csp_ctx *ctx, int d, long long N)
+{
+    if (ctx->path_override) return ctx->path_override;
+    const csp_ctx::Tuned *e = tuned_for(ctx, d, N);
+    return e ? e->path : 0;
+}
+
 int blocks_for(csp_ctx *ctx, int d, long long N)
 {
     if (ctx->blocks_override > 0) return std::min(ctx->blocks_override, ctx->max_blocks[d]);
+    if (const csp_ctx::Tuned *e = tuned_for(ctx, d, N)) return std::min(e->blocks, ctx->max_blocks[d]);
     // Few vertices: one workgroup (its barrier is a workgroup barrier).
     // Otherwise about one workgroup per 8K vertices, up to one per CU.
     long long want = (N + 8191) / 8192;
@@ -2726,7 +2750,7 @@ int blocks_for(csp_ctx *ctx, int d, long long N)
     return (int)std::max(1ll, std::min(want, (long long)ctx->max_blocks[d]));
 }
 
-LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M, int G_want)
+LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M, int G_want, int path)
 {
     LdsPlan pl;
     long long smax = 1;
@@ -2738,7 +2762,7 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
     // ship about a quarter of the candidates of whole-plane ranges but
     // measured slower on MI355X (more spread in per-range departure work),
     // so consecutive-index ranges are the default.
-    if (d == 3 && G_want >= 4 && ctx->path_override == 3) {
+    if (d == 3 && G_want >= 4 && path == 3) {
         int m = 1;
         while ((m + 1) * (m + 1) <= G_want) ++m;
         for (; m >= 2; --m) {
@@ -2970,9 +2994,10 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
 
     // Range-owned kernel when a range fits in LDS, else the global-label kernel.
     int G = blocks_for(ctx, d, N);
+    const int path = path_for(ctx, d, N);
     LdsPlan plan;
-    if (ctx->path_override != 2) {
-        plan = plan_lds(ctx, d, n, N, M, G);
+    if (path != 2) {
+        plan = plan_lds(ctx, d, n, N, M, G, path);
         if (plan.ok) {
             const void *kf = lds_kernel(d, plan.tile, log);
             if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds) != hipSuccess)
@@ -4162,6 +4187,84 @@ int csp_set_blocks(csp_ctx *ctx, int blocks)
 {
     if (!ctx || blocks < 0) return CSP_EINVAL;
     ctx->blocks_override = blocks;
+    return CSP_OK;
+}
+
+int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2, const uint8_t *A,
+                 const uint8_t *B, uint32_t M, int *blocks, int *path, float *ms, void *stream)
+{
+    if (!ctx || !f1 || !f2 || !A || !B) return fail(ctx, CSP_EINVAL, "null argument");
+    long long N = 0;
+    int rc = check_shape(ctx, d, n, M, N);
+    if (rc) return rc;
+    const int save_b = ctx->blocks_override, save_p = ctx->path_override;
+    auto forget = [&]() {
+        ctx->tuned.erase(std::remove_if(ctx->tuned.begin(), ctx->tuned.end(),
+                                        [&](const csp_ctx::Tuned &e) { return e.d == d && e.N == N; }),
+                         ctx->tuned.end());
+    };
+    forget();
+    ctx->blocks_override = 0;
+    ctx->path_override = 0;
+    // candidates: workgroup counts around the automatic choice; for d = 3
+    // also x-pencil ranges (path 0 is the automatic kernel choice)
+    const int b0 = blocks_for(ctx, d, N);
+    std::vector<int> bs;
+    for (int b : {b0, b0 / 2, b0 / 4, 2 * b0})
+        if (b >= 1 && b <= ctx->max_blocks[d] && std::find(bs.begin(), bs.end(), b) == bs.end()) bs.push_back(b);
+    std::vector<int> ps = {0};
+    if (d == 3) ps.push_back(3);
+    csp_result r0, r1;
+    csp_counters c0, c1;
+    bool have = false;
+    csp_ctx::Tuned best{d, N, b0, 0, 0.f}, base = best;
+    for (int pth : ps) {
+        for (int b : bs) {
+            ctx->blocks_override = b;
+            ctx->path_override = pth;
+            float t = -1.f;
+            for (int rep = 0; rep < 2 && rc == CSP_OK; ++rep) {
+                rc = solve_impl(ctx, d, n, f1, f2, A, B, M, nullptr, &r1, &c1, 0, stream, false);
+                if (rc == CSP_OK && (t < 0.f || ctx->last_ms < t)) t = ctx->last_ms;
+            }
+            if (rc == CSP_EINVAL && pth == 3) {         // pencils do not fit: not a candidate
+                rc = CSP_OK;
+                continue;
+            }
+            if (rc) {
+                ctx->blocks_override = save_b;
+                ctx->path_override = save_p;
+                return rc;
+            }
+            if (!have) {
+                r0 = r1;
+                c0 = c1;
+                have = true;
+                base = csp_ctx::Tuned{d, N, b, pth, t};      // the automatic configuration
+            } else if (memcmp(&r0, &r1, sizeof(r0)) != 0 || memcmp(&c0, &c1, sizeof(c0)) != 0) {
+                ctx->blocks_override = save_b;
+                ctx->path_override = save_p;
+                return fail(ctx, CSP_EDEVICE, "autotune: two configurations gave different results");
+            }
+            if (best.ms <= 0.f || t < best.ms) best = csp_ctx::Tuned{d, N, b, pth, t};
+        }
+    }
+    ctx->blocks_override = save_b;
+    ctx->path_override = save_p;
+    // another configuration replaces the automatic one only when it is at
+    // least 3 % faster, so that timing noise does not pick it
+    if (best.ms > 0.97f * base.ms) best = base;
+    ctx->tuned.push_back(best);
+    if (blocks) *blocks = best.blocks;
+    if (path) *path = best.path;
+    if (ms) *ms = best.ms;
+    return CSP_OK;
+}
+
+int csp_autotune_clear(csp_ctx *ctx)
+{
+    if (!ctx) return CSP_EINVAL;
+    ctx->tuned.clear();
     return CSP_OK;
 }
 
