@@ -75,6 +75,10 @@ def run_batch(args):
     torch.cuda.synchronize()
     solver = csp.Solver(0)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.autotune:
+        tgt, tms = csp.csp_autotune_batch(solver.ctx, dev, stream=stream)
+        tuned = {"vertices_per_workgroup": tgt, "kernel_ms": round(tms, 3)}
     for _ in range(args.warmup):
         csp.csp_solve_batch(solver.ctx, dev, stream=stream)
     torch.cuda.synchronize()
@@ -106,6 +110,8 @@ def run_batch(args):
                      "kernel_ms_avg": kms, "algorithmic_bytes_per_step": bytes_step},
         "cpu_baseline": None,
     }
+    if tuned:
+        line["autotune"] = tuned
     if args.plain:
         # the same problems as sequential single-problem launches
         torch.cuda.synchronize()
@@ -377,7 +383,8 @@ def main():
     ap.add_argument("--serve-fracs", type=float, nargs="*", default=[0.25, 0.5, 0.8])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
-                    help="lattice workloads: autotune each lattice shape before timing (traffic reported null)")
+                    help="lattice workloads: autotune each lattice shape before timing (traffic reported "
+                         "null); batch1024: autotune the gang size")
     ap.add_argument("--trace", action="store_true",
                     help="also report |I_t| and water in transit against t (one extra solve each, untimed)")
     args = ap.parse_args()

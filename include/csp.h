@@ -168,6 +168,22 @@ typedef struct {
 int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs,
                     csp_result *out, csp_counters *cnt, void *stream);
 
+/* Gang size of later batches on ctx: a problem of N vertices runs on about
+ * N / vertices_per_workgroup workgroups (more when its ranges would not fit
+ * LDS, fewer when neighbouring ranges would lie too far apart); 0, the
+ * default, gives every problem the fewest workgroups whose ranges fit LDS.
+ * Changes speed, never results. */
+int csp_set_batch_target(csp_ctx *ctx, int64_t vertices_per_workgroup);
+
+/* Autotuning of the batch: runs csp_solve_batch on the given problems with
+ * vertices_per_workgroup = 0, 65536, 32768, 16384 and 8192, checks that
+ * every run gives the same results and counters (else CSP_EDEVICE), and
+ * sets the fastest by kernel time (0 unless another is at least 3 % faster)
+ * as ctx's batch target.  target and ms (nullable) receive the choice and
+ * its kernel time in milliseconds.  csp_autotune_clear resets it to 0. */
+int csp_autotune_batch(csp_ctx *ctx, int count, const csp_problem *probs, int64_t *target, float *ms,
+                       void *stream);
+
 /* Device time (ms, from HIP events on the solve stream) of the cycle kernel
  * of the last successful csp_solve_dev on ctx; excludes input checks and
  * result copies. */
@@ -203,7 +219,7 @@ int csp_last_path(const csp_ctx *ctx);
  * unless csp_set_blocks or csp_set_path set an override.  blocks, path and
  * ms (nullable) receive the choice and its kernel time in milliseconds.
  * Tuning changes speed only, never results.  csp_autotune_clear drops every
- * recorded choice. */
+ * recorded choice (and resets the batch target, see csp_autotune_batch). */
 int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2, const uint8_t *A,
                  const uint8_t *B, uint32_t M, int *blocks, int *path, float *ms, void *stream);
 int csp_autotune_clear(csp_ctx *ctx);

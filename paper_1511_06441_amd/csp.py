@@ -29,6 +29,7 @@ EXPORTED = (
     "csp_last_path", "csp_solve_batch", "csp_serve_open", "csp_serve_submit",
     "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
     "csp_reconstruct_log_dev", "csp_solve_graph_dev", "csp_autotune", "csp_autotune_clear",
+    "csp_set_batch_target", "csp_autotune_batch",
 )
 
 
@@ -102,6 +103,10 @@ def _load():
     lib.csp_autotune.restype = i32
     lib.csp_autotune_clear.argtypes = [p]
     lib.csp_autotune_clear.restype = i32
+    lib.csp_set_batch_target.argtypes = [p, i64]
+    lib.csp_set_batch_target.restype = i32
+    lib.csp_autotune_batch.argtypes = [p, i32, p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float), p]
+    lib.csp_autotune_batch.restype = i32
     lib.csp_set_phase_timing.argtypes = [p, i32]
     lib.csp_set_phase_timing.restype = i32
     lib.csp_last_phase_us.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
@@ -206,14 +211,19 @@ def csp_reconstruct_dev(ctx, d, n, f1, f2, A, B, M, scratch_mask, cap, stream=No
     return path[:ln.value].copy(), res
 
 
-def csp_solve_batch(ctx, instances, labels=None, counters=True, stream=None):
-    """instances: list of DeviceInstance; labels: optional list of device int32 tensors (or None)."""
-    k = len(instances)
-    probs = (csp_problem * k)()
+def _problems(instances, labels=None):
+    probs = (csp_problem * len(instances))()
     for i, di in enumerate(instances):
         probs[i] = csp_problem(di.d, di.n, di.f1.data_ptr(), di.f2.data_ptr(), di.A.data_ptr(),
                                di.B.data_ptr(), di.M,
                                labels[i].data_ptr() if labels is not None and labels[i] is not None else None)
+    return probs
+
+
+def csp_solve_batch(ctx, instances, labels=None, counters=True, stream=None):
+    """instances: list of DeviceInstance; labels: optional list of device int32 tensors (or None)."""
+    k = len(instances)
+    probs = _problems(instances, labels)
     res = (csp_result * k)()
     cnt = (csp_counters * k)() if counters else None
     rc = lib.csp_solve_batch(ctx, k, ctypes.cast(probs, ctypes.c_void_p), ctypes.cast(res, ctypes.c_void_p),
@@ -255,6 +265,20 @@ def csp_autotune(ctx, d, n, f1, f2, A, B, M, stream=None):
 
 def csp_autotune_clear(ctx):
     _check(ctx, lib.csp_autotune_clear(ctx))
+
+
+def csp_set_batch_target(ctx, vertices_per_workgroup: int):
+    _check(ctx, lib.csp_set_batch_target(ctx, vertices_per_workgroup))
+
+
+def csp_autotune_batch(ctx, instances, stream=None):
+    """Time the batch gang-size candidates on these problems and keep the
+    fastest on ctx; returns (vertices per workgroup, kernel ms)."""
+    probs = _problems(instances)
+    tgt, ms = ctypes.c_int64(), ctypes.c_float()
+    _check(ctx, lib.csp_autotune_batch(ctx, len(instances), ctypes.cast(probs, ctypes.c_void_p),
+                                       ctypes.byref(tgt), ctypes.byref(ms), _stream(stream)))
+    return tgt.value, ms.value
 
 
 PHASES = ("departure", "barrier_after_departure", "next_time", "arrival",

@@ -2573,6 +2573,7 @@ struct csp_ctx {
         float ms;
     };
     std::vector<Tuned> tuned;
+    long long batch_target = 0;     // batch: vertices per workgroup (0 = fewest workgroups)
     long long *trace = nullptr;     // device [trace_cap][4], or null
     long long trace_cap = 0;
     long long last_trace_rows = 0;
@@ -3467,7 +3468,8 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
             pl.off[dir] = lower ? -stride[k] : stride[k];
         }
         GangPlan gp;
-        rc = plan_gang(ctx, budget, ctx->num_cu, q.d, q.n, N, q.M, gp);
+        const long long gw = ctx->batch_target > 0 ? (N + ctx->batch_target - 1) / ctx->batch_target : 0;
+        rc = plan_gang(ctx, budget, ctx->num_cu, q.d, q.n, N, q.M, gp, (int)std::min<long long>(gw, GMAX));
         if (rc) return rc;
         pl.c = gp.c;
         pl.g = gp.g;
@@ -4265,6 +4267,70 @@ int csp_autotune_clear(csp_ctx *ctx)
 {
     if (!ctx) return CSP_EINVAL;
     ctx->tuned.clear();
+    ctx->batch_target = 0;
+    return CSP_OK;
+}
+
+int csp_set_batch_target(csp_ctx *ctx, int64_t vertices_per_workgroup)
+{
+    if (!ctx || vertices_per_workgroup < 0) return CSP_EINVAL;
+    ctx->batch_target = vertices_per_workgroup;
+    return CSP_OK;
+}
+
+int csp_autotune_batch(csp_ctx *ctx, int count, const csp_problem *probs, int64_t *target, float *ms,
+                       void *stream)
+{
+    if (!ctx || count < 1 || !probs) return fail(ctx, CSP_EINVAL, "null argument");
+    const long long save = ctx->batch_target;
+    std::vector<csp_result> r0((size_t)count), r1((size_t)count);
+    std::vector<csp_counters> c0((size_t)count), c1((size_t)count);
+    long long best_t = 0;
+    float best_ms = -1.f, base_ms = -1.f;
+    bool have = false;
+    for (long long tgt : {0ll, 65536ll, 32768ll, 16384ll, 8192ll}) {
+        ctx->batch_target = tgt;
+        float t = -1.f;
+        int rc = CSP_OK;
+        for (int rep = 0; rep < (have ? 1 : 2) && rc == CSP_OK; ++rep) {   // the first run also warms the arena
+            rc = csp_solve_batch(ctx, count, probs, r1.data(), c1.data(), stream);
+            if (rc == CSP_OK) t = ctx->last_ms;
+        }
+        if (rc) {
+            ctx->batch_target = save;
+            return rc;
+        }
+        if (!have) {
+            r0 = r1;
+            c0 = c1;
+            have = true;
+            base_ms = t;
+        } else {
+            for (int i = 0; i < count; ++i) {
+                if (memcmp(&r0[i], &r1[i], sizeof(csp_result)) == 0 && memcmp(&c0[i], &c1[i], sizeof(csp_counters)) == 0)
+                    continue;
+                char msg[200];
+                snprintf(msg, sizeof(msg),
+                         "autotune: batch problem %d differs at %lld vertices per workgroup "
+                         "(T %lld/%lld, U %lld/%lld, P %lld/%lld, I %lld/%lld)",
+                         i, tgt, (long long)r0[i].T, (long long)r1[i].T, (long long)c0[i].U, (long long)c1[i].U,
+                         (long long)c0[i].P, (long long)c1[i].P, (long long)c0[i].I, (long long)c1[i].I);
+                ctx->batch_target = save;
+                return fail(ctx, CSP_EDEVICE, msg);
+            }
+        }
+        if (best_ms < 0.f || t < best_ms) {
+            best_ms = t;
+            best_t = tgt;
+        }
+    }
+    if (best_ms > 0.97f * base_ms) {        // keep the fewest-workgroup plan unless clearly slower
+        best_ms = base_ms;
+        best_t = 0;
+    }
+    ctx->batch_target = best_t;
+    if (target) *target = best_t;
+    if (ms) *ms = best_ms;
     return CSP_OK;
 }
 

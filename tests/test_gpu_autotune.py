@@ -105,3 +105,37 @@ def test_autotune_rejects_bad_input(solver, torch):
     # nothing was recorded by the failed calls: the solve still runs as before
     res, cnt, _ = _solve(solver, torch, di, inst.N)
     assert res.T == 142
+
+
+@pytest.mark.parametrize("target", [8192, 65536])
+def test_batch_target_keeps_results(solver, torch, target):
+    """Gang sizes from an explicit target give the oracle's results."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(43, j, lo2=(32, 400), lo3=(12, 48)) for j in range(24)]
+    dev = [csp.to_device(i) for i in insts]
+    csp.csp_set_batch_target(solver.ctx, target)
+    try:
+        res, cnt = csp.csp_solve_batch(solver.ctx, dev)
+    finally:
+        csp.csp_set_batch_target(solver.ctx, 0)
+    _say("batch target", target, "kernel ms %.3f" % csp.csp_last_kernel_ms(solver.ctx))
+    for inst, r, c in zip(insts, res, cnt):
+        ref = O.solve_instance(inst, want_labels=False)
+        assert r.tuple() == ref.tuple() and c.asdict() == ref.counters, inst.name
+
+
+def test_autotune_batch(solver, torch):
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(44, j, lo2=(32, 400), lo3=(12, 48)) for j in range(32)]
+    dev = [csp.to_device(i) for i in insts]
+    base, bcnt = csp.csp_solve_batch(solver.ctx, dev)
+    tgt, ms = csp.csp_autotune_batch(solver.ctx, dev)
+    _say("batch autotune: vertices per workgroup", tgt, "ms %.3f" % ms)
+    assert tgt in (0, 65536, 32768, 16384, 8192) and ms > 0
+    res, cnt = csp.csp_solve_batch(solver.ctx, dev)
+    assert [r.tuple() for r in res] == [r.tuple() for r in base]
+    assert [c.asdict() for c in cnt] == [c.asdict() for c in bcnt]
+    csp.csp_autotune_clear(solver.ctx)
+    with pytest.raises(csp.CspError):
+        csp.csp_set_batch_target(solver.ctx, -1)
