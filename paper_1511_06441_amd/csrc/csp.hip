@@ -1655,7 +1655,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             s_sum = 0;
             s_nl = 0;
             s_bhn = 0;
-            s_flags &= SF_OVER;
+            // atomic: other threads may still be flagging an overflow of the
+            // candidate phase, and a lost flag would drop flows silently
+            atomicAnd(&s_flags, SF_OVER);
             s_xkey = 0;
         }
         __syncthreads();
@@ -2880,6 +2882,9 @@ int plan_gang(csp_ctx *ctx, size_t budget, int gmax, int d, long long n, long lo
     if (pl.c > cmax) return fail(ctx, CSP_EINVAL, "problem too large for one launch");
     pl.K = pl.g == 1 ? 0 : (int)((smax + pl.c - 1) / pl.c);
     if (pl.K > KMAX) return fail(ctx, CSP_EINVAL, "problem ranges too thin");
+    // 32-bit labels (one atomicMax per raise) when the range fits with them;
+    // 16-bit labels take a compare-and-swap loop
+    if (pl.lt == 2 && lds_bytes_for(pl.c, pl.K, 4) <= budget) pl.lt = 4;
     pl.lds = lds_bytes_for(pl.c, pl.K, pl.lt);
     pl.llist = (int)lds_list_cap(pl.c, pl.lds, budget);
     pl.lds += lds_list_bytes(pl.llist);

@@ -110,3 +110,24 @@ def test_config4_sample_vs_plain(solver, torch):
         r1, c1 = solver.solve(di)
         assert r.tuple() == r1.tuple() and c.asdict() == c1.asdict(), inst.name
         assert r.T < 0 or 0 < r.F2 < inst.M
+
+
+def test_candidate_phase_overflow_always_retried(solver, torch):
+    """A gang of 27 ranges on this 60^3 lattice (8,192 vertices per
+    workgroup) overflows a wheel bucket while it accepts candidates.  The
+    overflow must send the problem round again every time: when thread 0
+    cleared the flag word non-atomically, the flag was sometimes lost and
+    flows were dropped without a retry (about one run in three)."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    inst = gen.mixed_instance(41, 639)
+    ref = O.solve_instance(inst, want_labels=False)
+    dev = [csp.to_device(inst)]
+    csp.csp_set_batch_target(solver.ctx, 8192)
+    try:
+        for k in range(60):
+            res, cnt = csp.csp_solve_batch(solver.ctx, dev)
+            assert res[0].tuple() == ref.tuple(), k
+            assert cnt[0].asdict() == ref.counters, (k, cnt[0].asdict(), ref.counters)
+    finally:
+        csp.csp_set_batch_target(solver.ctx, 0)
