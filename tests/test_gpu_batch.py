@@ -72,6 +72,30 @@ def test_gangs_vs_oracle(solver, torch):
         _check_vs_oracle(inst, r, c, l)
 
 
+def test_all_dimensions_and_extreme_M(solver, torch):
+    """d = 1..4 in one batch (one persistent launch per dimension), with M = 1,
+    M on both sides of the 16-bit label limit, the largest M, a corner-to-
+    corner problem, and a 4-d problem that needs a gang."""
+    insts = [gen.opposite_faces(1, 200, 1, 9, 9, 500), gen.opposite_faces(1, 7, 2, 3, 3, 1),
+             gen.opposite_faces(4, 6, 3, 5, 5, 40), gen.opposite_faces(4, 9, 4, 8, 8, 0x0FFFFFFF),
+             gen.opposite_faces(2, 40, 5, 5, 5, 65535), gen.opposite_faces(2, 40, 6, 5, 5, 65536),
+             gen.opposite_faces(3, 20, 7, 9, 9, 70001), gen.opposite_faces(4, 24, 8, 7, 7, 400),
+             gen.opposite_faces(1, 2, 9, 4, 4, 10)]
+    corner = gen.opposite_faces(3, 17, 10, 6, 6, 200)
+    corner.A = np.zeros(corner.N, np.uint8)
+    corner.A[0] = 1
+    corner.B = np.zeros(corner.N, np.uint8)
+    corner.B[corner.N - 1] = 1
+    insts.append(corner)
+    for i, inst in enumerate(insts):
+        inst.name = f"dims{i}_d{inst.d}_n{inst.n}_M{inst.M}"
+    _say("all-dimension batch of", len(insts))
+    res, cnt, labs = _batch(solver, torch, insts)
+    for inst, r, c, l in zip(insts, res, cnt, labs):
+        _check_vs_oracle(inst, r, c, l)
+    assert res[1].T == -1                                   # M = 1: no water leaves A
+
+
 def test_batch_equals_alone(solver, torch):
     from paper_1511_06441_amd import csp
     insts = [gen.mixed_instance(41, j, lo2=(16, 200), lo3=(8, 40)) for j in range(24)]

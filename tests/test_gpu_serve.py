@@ -118,6 +118,20 @@ def test_serve_alone_equals_mix(server, torch):
         assert _key(alone[k]) == _key(mixed[k]), insts[k].name
 
 
+def test_serve_dimensions_one_and_four(server, torch):
+    """1-d and 4-d requests (one of them needing a gang) with their paths."""
+    from paper_1511_06441_amd import csp
+    insts = [gen.opposite_faces(1, 300, 61, 9, 9, 900), gen.opposite_faces(4, 7, 62, 5, 5, 60),
+             gen.opposite_faces(4, 20, 63, 6, 6, 300), gen.opposite_faces(1, 9, 64, 4, 4, 2)]
+    done = _run_all(server, [csp.to_device(i) for i in insts], stagger=2)
+    for k, inst in enumerate(insts):
+        ref, path = _oracle_request(inst)
+        c = done[k]
+        assert c.status == 0, (k, c.status)
+        assert c.res == ref.tuple() and c.counters == ref.counters, k
+        assert c.path == path, k
+
+
 def test_serve_without_reconstruction(server, torch):
     from oracle import oracle as O
     from paper_1511_06441_amd import csp
