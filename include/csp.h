@@ -123,7 +123,9 @@ int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n,
  * eid int64 [m] (the edge id reported as x; equal on the two copies of an
  * edge); A, B uint8 [nv]; labels uint32 [nv] (nullable).  m = off[nv].
  * Results, counters and errors as for csp_solve_dev; x is eid of the last
- * edge.  Labels live in HBM (no LDS ranges). */
+ * edge.  CSP_EINVAL also when off is not non-decreasing within [0, m] or a
+ * neighbour index lies outside [0, nv) (checked on the device before any
+ * cycle runs).  Labels live in HBM (no LDS ranges). */
 int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off,
                         const int32_t *nbr, const uint8_t *f1, const uint8_t *f2,
                         const int64_t *eid, const uint8_t *A, const uint8_t *B,

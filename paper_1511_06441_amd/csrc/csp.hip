@@ -2221,9 +2221,17 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
         for (long long v = lo + tid; v < hi; v += BLOCK) {
             const bool a = p.A[v] != 0, b = p.B[v] != 0;
             if (a && b) bad |= 2;
-            for (long long j = p.off[v]; j < p.off[v + 1]; ++j) {
+            // the adjacency arrays are checked here, before any cycle reads
+            // them: entries j0 .. j1 - 1 must lie in [0, m) and name vertices
+            const long long j0 = p.off[v], j1 = p.off[v + 1];
+            if (j0 < 0 || j1 < j0 || j1 > p.m) {
+                bad |= 2;
+                continue;
+            }
+            for (long long j = j0; j < j1; ++j) {
                 const unsigned x1 = p.f1[j], x2 = p.f2[j];
                 if (!x1 || !x2) bad |= 1;
+                if (p.nbr[j] < 0 || (long long)p.nbr[j] >= nv) bad |= 2;
                 mf = x1 > mf ? x1 : mf;
             }
             p.lab[v] = a ? p.M : 0u;
@@ -2954,7 +2962,9 @@ void csp_destroy(csp_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     for (void *p : {(void *)ctx->lab, (void *)ctx->rec, (void *)ctx->queue, (void *)ctx->pool,
                     (void *)ctx->ctl, (void *)ctx->in_buf, (void *)ctx->pub, (void *)ctx->cand,
-                    (void *)ctx->arena})
+                    (void *)ctx->arena, (void *)ctx->gstamp, (void *)ctx->glists, (void *)ctx->gpool,
+                    (void *)ctx->wptr, (void *)ctx->cptr, (void *)ctx->cur, (void *)ctx->winner,
+                    (void *)ctx->logbuf, (void *)ctx->walk})
         if (p) (void)hipFree(p);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     for (void *p : {(void *)ctx->h_ctl, (void *)ctx->h_byte})
@@ -3270,7 +3280,9 @@ int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int3
         }
         HIP_TRY(hipStreamSynchronize(s), "graph solve");
         const Out &o = ctx->h_ctl->rout;
-        if (o.status == ST_INVAL) return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0, or A and B overlap");
+        if (o.status == ST_INVAL)
+            return fail(ctx, CSP_EINVAL,
+                        "an edge has f1 or f2 equal to 0, A and B overlap, or off / nbr are out of range");
         if (o.status == ST_OVERFLOW) {
             if (pool >= pool_max)
                 return fail(ctx, CSP_EOVERFLOW, "graph transit pool overflow at the edge bound");

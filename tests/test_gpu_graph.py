@@ -134,3 +134,18 @@ def test_graph_invalid_inputs(solver, torch):
     A2[np.argmax(B)] = 1
     with pytest.raises(csp.CspError):
         _gpu(solver, torch, 50, edges, A2, B, 40)
+    # malformed adjacency arrays (same sizes, so every read stays inside
+    # them): a neighbour index past the last vertex, and a decreasing offset
+    off, nbr, f1, f2, eid = gen.graph_csr(50, *edges[:4])
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    for what in ("nbr", "off"):
+        o2, n2 = off.copy(), nbr.copy()
+        if what == "nbr":
+            n2[3] = 50 + 7
+        else:
+            o2[10] = o2[11] + 1
+            assert o2[10] <= o2[-1]
+        g = csp.graph_to_device((o2, n2, f1, f2, eid))
+        with pytest.raises(csp.CspError) as e:
+            csp.csp_solve_graph_dev(solver.ctx, g, At, Bt, 40)
+        assert e.value.code == csp.CSP_EINVAL, what
