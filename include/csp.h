@@ -108,6 +108,13 @@ int csp_solve(csp_ctx *ctx, int d, int64_t n,
  * path gives *len = 0.  Inputs are device pointers as for csp_solve_dev.
  * `scratch_mask` is a caller-owned device uint8 [N] used for B'; it must be
  * all zero on entry and is all zero again on return. */
+/* Same on host buffers (inputs as for csp_solve; the B' mask lives in ctx).
+ * Synchronous. */
+int csp_reconstruct(csp_ctx *ctx, int d, int64_t n,
+                    const uint8_t *f1, const uint8_t *f2,
+                    const uint8_t *A, const uint8_t *B, uint32_t M,
+                    int64_t *path, int64_t cap, int64_t *len, csp_result *out);
+
 int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n,
                         const uint8_t *f1, const uint8_t *f2,
                         const uint8_t *A, const uint8_t *B, uint32_t M,

@@ -29,7 +29,7 @@ EXPORTED = (
     "csp_last_path", "csp_solve_batch", "csp_serve_open", "csp_serve_submit",
     "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
     "csp_reconstruct_log_dev", "csp_solve_graph_dev", "csp_autotune", "csp_autotune_clear",
-    "csp_set_batch_target", "csp_autotune_batch",
+    "csp_set_batch_target", "csp_autotune_batch", "csp_reconstruct",
 )
 
 
@@ -103,6 +103,9 @@ def _load():
     lib.csp_autotune.restype = i32
     lib.csp_autotune_clear.argtypes = [p]
     lib.csp_autotune_clear.restype = i32
+    lib.csp_reconstruct.argtypes = [p, i32, i64, p, p, p, p, u32, p, i64, ctypes.POINTER(i64),
+                                    ctypes.POINTER(csp_result)]
+    lib.csp_reconstruct.restype = i32
     lib.csp_set_batch_target.argtypes = [p, i64]
     lib.csp_set_batch_target.restype = i32
     lib.csp_autotune_batch.argtypes = [p, i32, p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float), p]
@@ -197,6 +200,19 @@ def csp_solve(ctx, d, n, f1, f2, A, B, M, labels=None):
                        ctypes.byref(res), ctypes.byref(cnt))
     _check(ctx, rc)
     return res, cnt
+
+
+def csp_reconstruct(ctx, d, n, f1, f2, A, B, M, cap):
+    """Host numpy inputs; returns (path int64 array A -> X, result)."""
+    import numpy as np
+    path = np.zeros(max(int(cap), 1), dtype=np.int64)
+    ln = ctypes.c_int64()
+    res = csp_result()
+    addr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    rc = lib.csp_reconstruct(ctx, d, n, addr(f1), addr(f2), addr(A), addr(B), M, addr(path), int(cap),
+                             ctypes.byref(ln), ctypes.byref(res))
+    _check(ctx, rc)
+    return path[:ln.value].copy(), res
 
 
 def csp_reconstruct_dev(ctx, d, n, f1, f2, A, B, M, scratch_mask, cap, stream=None):

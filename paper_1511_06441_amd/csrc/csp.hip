@@ -3376,6 +3376,34 @@ int csp_solve(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *
     return CSP_OK;
 }
 
+int csp_reconstruct(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2, const uint8_t *A,
+                    const uint8_t *B, uint32_t M, int64_t *path, int64_t cap, int64_t *len, csp_result *out)
+{
+    if (!ctx || !out || !f1 || !f2 || !A || !B || !path || !len) return fail(ctx, CSP_EINVAL, "null argument");
+    long long N = 0;
+    int rc = check_shape(ctx, d, n, M, N);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    // staging: f1 | f2 | A | B | the B' mask of the re-solves, each region 256-byte aligned
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t fbytes = (size_t)d * N;
+    const size_t o_f2 = up(fbytes), o_A = o_f2 + up(fbytes), o_B = o_A + up(N), o_S = o_B + up(N);
+    const size_t need = o_S + up(N);
+    rc = grow(ctx, &ctx->in_buf, ctx->in_cap, need, "input staging");
+    if (rc) return rc;
+    uint8_t *df1 = ctx->in_buf, *df2 = ctx->in_buf + o_f2, *dA = ctx->in_buf + o_A, *dB = ctx->in_buf + o_B;
+    uint8_t *dS = ctx->in_buf + o_S;
+    HIP_TRY(hipMemcpy(df1, f1, fbytes, hipMemcpyHostToDevice), "upload f1");
+    HIP_TRY(hipMemcpy(df2, f2, fbytes, hipMemcpyHostToDevice), "upload f2");
+    HIP_TRY(hipMemcpy(dA, A, N, hipMemcpyHostToDevice), "upload A");
+    HIP_TRY(hipMemcpy(dB, B, N, hipMemcpyHostToDevice), "upload B");
+    const unsigned long long words = up(N) / 4;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<unsigned long long>((words + 255) / 256, 1024ull)), dim3(256),
+                       0, (hipStream_t) nullptr, reinterpret_cast<unsigned *>(dS), words);
+    HIP_TRY(hipGetLastError(), "clear mask");
+    return csp_reconstruct_dev(ctx, d, n, df1, df2, dA, dB, M, dS, path, cap, len, out, nullptr);
+}
+
 int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
                         const uint8_t *A, const uint8_t *B, uint32_t M, uint8_t *scratch_mask,
                         int64_t *path, int64_t cap, int64_t *len, csp_result *out, void *stream)

@@ -330,6 +330,25 @@ def test_reconstruct_vs_oracle(solver, torch, case):
     assert int(scratch.sum().item()) == 0
 
 
+@pytest.mark.parametrize("case", [(2, 12, 1, 5, 5, 50), (3, 9, 5, 10, 10, 90), (4, 5, 6, 6, 6, 40),
+                                  (2, 17, 8, 5, 5, 5)])
+def test_reconstruct_host_buffers_vs_oracle(solver, torch, case):
+    """csp_reconstruct on host arrays gives the oracle's path and result;
+    a path buffer that is too short is refused with the needed length."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    d, n, seed, K1, K2, M = case
+    inst = gen.opposite_faces(d, n, seed, K1, K2, M)
+    path_ref, res_ref, _ = O.reconstruct(d, n, inst.f1, inst.f2, inst.A, inst.B, M)
+    path, res = csp.csp_reconstruct(solver.ctx, d, n, inst.f1, inst.f2, inst.A, inst.B, M, inst.N + 1)
+    assert res.tuple() == res_ref.tuple()
+    assert path.tolist() == [int(v) for v in path_ref]
+    if len(path_ref) > 1:
+        with pytest.raises(csp.CspError) as e:
+            csp.csp_reconstruct(solver.ctx, d, n, inst.f1, inst.f2, inst.A, inst.B, M, 1)
+        assert e.value.code == csp.CSP_EINVAL
+
+
 # ---------------------------------------------------------------------------
 # path recovery from the improvement log (one solve, then a walk back)
 # ---------------------------------------------------------------------------
