@@ -173,7 +173,8 @@ typedef struct {
  * themselves.  Results (and counters, nullable) are written per problem in
  * input order, identical to csp_solve_dev on each problem alone.  Returns
  * the first error; problems whose wheel overflows are re-run with larger
- * pools automatically.  Synchronous on `stream`. */
+ * pools automatically, and ctx remembers those sizes for the same problem
+ * (shape, M and input pointers) in later batches.  Synchronous on `stream`. */
 int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs,
                     csp_result *out, csp_counters *cnt, void *stream);
 
@@ -228,7 +229,8 @@ int csp_last_path(const csp_ctx *ctx);
  * unless csp_set_blocks or csp_set_path set an override.  blocks, path and
  * ms (nullable) receive the choice and its kernel time in milliseconds.
  * Tuning changes speed only, never results.  csp_autotune_clear drops every
- * recorded choice (and resets the batch target, see csp_autotune_batch). */
+ * recorded choice (and resets the batch target, see csp_autotune_batch, and
+ * the batch sizes remembered per problem, see csp_solve_batch). */
 int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2, const uint8_t *A,
                  const uint8_t *B, uint32_t M, int *blocks, int *path, float *ms, void *stream);
 int csp_autotune_clear(csp_ctx *ctx);

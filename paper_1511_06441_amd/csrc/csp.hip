@@ -58,6 +58,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <vector>
 
 #include "csp.h"
@@ -2584,6 +2585,12 @@ struct csp_ctx {
     };
     std::vector<Tuned> tuned;
     long long batch_target = 0;     // batch: vertices per workgroup (0 = fewest workgroups)
+    // batch: wheel pool and candidate capacity a problem (same lattice, masks
+    // and M at the same addresses) needed in an earlier batch, so a repeated
+    // problem starts with them instead of overflowing and running again
+    std::map<std::tuple<int, long long, unsigned, const void *, const void *, const void *, const void *>,
+             std::pair<unsigned long long, unsigned long long>>
+        batch_seen;
     long long *trace = nullptr;     // device [trace_cap][4], or null
     long long trace_cap = 0;
     long long last_trace_rows = 0;
@@ -3524,6 +3531,15 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
         pl.lds = gp.lds;
         pl.pool = gp.pool;
         pl.ccap = gp.ccap;
+        if (!ctx->pool_hint) {
+            const auto it = ctx->batch_seen.find(std::make_tuple(q.d, (long long)q.n, q.M, (const void *)q.f1,
+                                                                 (const void *)q.f2, (const void *)q.A,
+                                                                 (const void *)q.B));
+            if (it != ctx->batch_seen.end()) {
+                pl.pool = std::max(pl.pool, it->second.first);
+                pl.ccap = std::max(pl.ccap, it->second.second);
+            }
+        }
         todo[i] = i;
     }
 
@@ -3686,6 +3702,13 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
             }
             if (o.status == ST_INVAL) return fail(ctx, CSP_EINVAL, "batch problem has a zero edge or A and B overlap");
             if (o.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "batch problem did not finish");
+            if (rounds > 1 && !ctx->pool_hint) {
+                // this problem overflowed at the starting sizes: remember what it needed
+                if (ctx->batch_seen.size() >= 65536) ctx->batch_seen.clear();
+                const csp_problem &q = probs[i];
+                ctx->batch_seen[std::make_tuple(q.d, (long long)q.n, q.M, (const void *)q.f1, (const void *)q.f2,
+                                                (const void *)q.A, (const void *)q.B)] = {plan[i].pool, plan[i].ccap};
+            }
             out[i].T = o.res[0];
             out[i].X = o.res[1];
             out[i].x = o.res[2];
@@ -4313,6 +4336,7 @@ int csp_autotune_clear(csp_ctx *ctx)
     if (!ctx) return CSP_EINVAL;
     ctx->tuned.clear();
     ctx->batch_target = 0;
+    ctx->batch_seen.clear();
     return CSP_OK;
 }
 

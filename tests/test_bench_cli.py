@@ -21,17 +21,21 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_read_only_for_the_current_source(tmp_path, monkeypatch):
-    # the committed summaries match the committed source
-    assert bench.measured_traffic("cube128") is not None
-    # a summary recorded for another source is ignored
+    import hashlib
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "k_ranges3_cube128_traffic.md").write_text(
-        "traffic_bytes_per_launch: 1.0e9\ncsp_hip_sha256: " + "0" * 64 + "\n")
     src = tmp_path / "paper_1511_06441_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "csp.hip").write_bytes(open(os.path.join(ROOT, "paper_1511_06441_amd", "csrc", "csp.hip"), "rb").read())
+    (src / "csp.hip").write_bytes(b"// kernel source\n")
+    good = hashlib.sha256(b"// kernel source\n").hexdigest()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # a summary recorded for this source is used
+    (prof / "k_ranges3_cube128_traffic.md").write_text(
+        "traffic_bytes_per_launch: 1.5e9\ncsp_hip_sha256: " + good + "\n")
+    assert bench.measured_traffic("cube128") == 1.5e9
+    # one recorded for another source is ignored
+    (prof / "k_ranges3_cube128_traffic.md").write_text(
+        "traffic_bytes_per_launch: 1.5e9\ncsp_hip_sha256: " + "0" * 64 + "\n")
     assert bench.measured_traffic("cube128") is None
     assert bench.measured_traffic("square64") is None           # no summary at all
 

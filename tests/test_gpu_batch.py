@@ -96,6 +96,26 @@ def test_all_dimensions_and_extreme_M(solver, torch):
     assert res[1].T == -1                                   # M = 1: no water leaves A
 
 
+def test_repeated_batch_with_remembered_sizes(solver, torch):
+    """The second run of a batch starts with the pool sizes the first one
+    grew to; results and counters are the same and equal the oracle's."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    insts = [gen.mixed_instance(45, j, lo2=(16, 120), lo3=(8, 30)) for j in range(40)]
+    dev = [csp.to_device(i) for i in insts]
+    csp.csp_autotune_clear(solver.ctx)
+    r1, c1 = csp.csp_solve_batch(solver.ctx, dev)
+    ms1 = csp.csp_last_kernel_ms(solver.ctx)
+    r2, c2 = csp.csp_solve_batch(solver.ctx, dev)
+    ms2 = csp.csp_last_kernel_ms(solver.ctx)
+    _say("first run %.2f ms, second %.2f ms" % (ms1, ms2))
+    for inst, a, b, ca, cb in zip(insts, r1, r2, c1, c2):
+        ref = O.solve_instance(inst, want_labels=False)
+        assert a.tuple() == b.tuple() == ref.tuple(), inst.name
+        assert ca.asdict() == cb.asdict() == ref.counters, inst.name
+    csp.csp_autotune_clear(solver.ctx)
+
+
 def test_batch_equals_alone(solver, torch):
     from paper_1511_06441_amd import csp
     insts = [gen.mixed_instance(41, j, lo2=(16, 200), lo3=(8, 40)) for j in range(24)]
@@ -150,6 +170,9 @@ def test_candidate_phase_overflow_always_retried(solver, torch):
     csp.csp_set_batch_target(solver.ctx, 8192)
     try:
         for k in range(60):
+            # forget the sizes the overflow taught, so every run starts small
+            csp.csp_autotune_clear(solver.ctx)
+            csp.csp_set_batch_target(solver.ctx, 8192)
             res, cnt = csp.csp_solve_batch(solver.ctx, dev)
             assert res[0].tuple() == ref.tuple(), k
             assert cnt[0].asdict() == ref.counters, (k, cnt[0].asdict(), ref.counters)
