@@ -195,8 +195,9 @@ int csp_autotune_batch(csp_ctx *ctx, int count, const csp_problem *probs, int64_
                        void *stream);
 
 /* Device time (ms, from HIP events on the solve stream) of the cycle kernel
- * of the last successful csp_solve_dev on ctx; excludes input checks and
- * result copies. */
+ * of the last successful solve on ctx (csp_solve_dev, csp_solve,
+ * csp_solve_graph_dev; for csp_solve_batch the sum over its launches and
+ * retry rounds); excludes input checks and result copies. */
 int csp_last_kernel_ms(const csp_ctx *ctx, float *ms);
 
 /* Starting capacity of each timing-wheel bucket, in flows (0 = automatic).
