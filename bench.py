@@ -378,9 +378,9 @@ def main():
     ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["batch1024", "serve", "recon", "graph128"])
     ap.add_argument("--batch-count", type=int, default=1024)
     ap.add_argument("--plain", action="store_true", help="batch workload: also time sequential plain launches")
-    ap.add_argument("--serve-count", type=int, default=32)
+    ap.add_argument("--serve-count", type=int, default=8)
     ap.add_argument("--serve-arena-gb", type=int, default=64)
-    ap.add_argument("--serve-fracs", type=float, nargs="*", default=[0.25, 0.5, 0.8])
+    ap.add_argument("--serve-fracs", type=float, nargs="*", default=[0.5, 0.8])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="lattice workloads: autotune each lattice shape before timing (traffic reported "
