@@ -188,105 +188,151 @@ def states_solve(nv, edges, A, B, M):
 # P3: time-indexed recurrence, with the cycle's counters
 # ----------------------------------------------------------------------------
 
+def _in_slots(nv, edges):
+    """Incoming directed edges grouped in slots: slot j holds the j-th
+    incoming edge of every vertex that has more than j, so the destinations
+    of one slot are distinct.  Each slot: (dst, src, f1, f2) arrays."""
+    us, vs, w1, w2, _ids = edges
+    src = np.concatenate([us, vs]).astype(np.int64)
+    dst = np.concatenate([vs, us]).astype(np.int64)
+    a1 = np.concatenate([w1, w1]).astype(np.int64)
+    a2 = np.concatenate([w2, w2]).astype(np.int64)
+    order = np.lexsort((src, dst))
+    src, dst, a1, a2 = src[order], dst[order], a1[order], a2[order]
+    first = np.searchsorted(dst, dst, side="left")
+    rank = np.arange(dst.size) - first
+    slots = []
+    for j in range(int(rank.max()) + 1 if rank.size else 0):
+        m = rank == j
+        slots.append((dst[m], src[m], a1[m], a2[m]))
+    deg = np.bincount(src, minlength=nv)
+    return slots, deg
+
+
 def dp_solve(nv, edges, A, B, M, t_limit=1 << 20):
     """Run L_t for t = 0, 1, ... and enumerate the flows the cycle would send.
 
     A vertex Q whose label rose at time s (A at s = 0) sends over (Q, P) iff
     L_s(Q) - f2 > L_s(P); the flow arrives at s + f1.  The run stops at the
-    answer time T, or when nothing is in transit.
+    answer time T, or when nothing is in transit.  Only the last max-f1 + 1
+    label vectors are kept, so it scales to lattices of millions of vertices.
 
-    Returns dict with T, X, x, Y, F2, labels (L_T), counters C U D E R P I.
+    Returns dict with T, X, x, Y, F2, labels (L_T), counters C U D E R P I,
+    and rows: one (t, delivered, |I_t|, sent) per time with deliveries.
     """
     us, vs, w1, w2, ids = edges
-    # directed copies
-    src = np.concatenate([us, vs])
-    dst = np.concatenate([vs, us])
-    a1 = np.concatenate([w1, w1])
-    a2 = np.concatenate([w2, w2])
-    deg = np.bincount(src, minlength=nv)
-    fmax = int(a1.max()) if a1.size else 1
+    slots, deg = _in_slots(nv, edges)
+    fmax = max((int(s[2].max()) for s in slots), default=1)
+    W = fmax + 1
     Aidx = np.nonzero(A)[0]
     Bm = np.asarray(B).astype(bool)
+    # outgoing directed copies, grouped by source (for the sends of I_s)
+    osrc = np.concatenate([us, vs]).astype(np.int64)
+    odst = np.concatenate([vs, us]).astype(np.int64)
+    oa1 = np.concatenate([w1, w1]).astype(np.int64)
+    oa2 = np.concatenate([w2, w2]).astype(np.int64)
+    order = np.argsort(osrc, kind="stable")
+    osrc, odst, oa1, oa2 = osrc[order], odst[order], oa1[order], oa2[order]
+    ostart = np.searchsorted(osrc, np.arange(nv + 1))
 
-    hist = []                                   # L_s for every s so far
-    L0 = np.zeros(nv, dtype=np.int64)
-    L0[Aidx] = M
-    hist.append(L0)
-    arrivals = {}                               # time -> number of flows arriving
-    C = U = D = E = 0
-    maxI = 0
-    in_transit_by_time = []                     # flows in transit after sending at s
-    sent_log = []                               # (send time, arrival time)
+    ring = np.zeros((W, nv), dtype=np.int64)        # ring[s % W] = L_s
+    ring[0, Aidx] = M
+    arrive = np.zeros(1024, dtype=np.int64)          # flows arriving at each time
+    sent = np.zeros(1024, dtype=np.int64)            # flows sent at each time
+
+    def grow(a, need):
+        if need < a.size:
+            return a
+        b = np.zeros(max(need + 1, 2 * a.size), dtype=np.int64)
+        b[:a.size] = a
+        return b
 
     def send(s, Ls, improved):
-        nonlocal D, E
+        """Flows from the vertices of I_s; returns (tests, flows)."""
+        nonlocal arrive, sent
         if improved.size == 0:
-            return
-        D += int(deg[improved].sum())
-        mask = np.zeros(nv, dtype=bool)
-        mask[improved] = True
-        sel = mask[src] & (Ls[src] - a2 > Ls[dst])
-        E += int(sel.sum())
-        for ta in (s + a1[sel]).tolist():
-            arrivals[ta] = arrivals.get(ta, 0) + 1
-            sent_log.append((s, ta))
+            return 0, 0
+        lo, hi = ostart[improved], ostart[improved + 1]
+        cnt = hi - lo
+        idx = np.repeat(lo - (np.cumsum(cnt) - cnt), cnt) + np.arange(int(cnt.sum()))
+        ok = Ls[osrc[idx]] - oa2[idx] > Ls[odst[idx]]
+        ta = s + oa1[idx[ok]]
+        if ta.size:
+            arrive = grow(arrive, int(ta.max()))
+            arrive += np.bincount(ta, minlength=arrive.size)[:arrive.size]
+        sent = grow(sent, s)
+        sent[s] = int(ok.sum())
+        return int(cnt.sum()), int(ok.sum())
 
-    U += Aidx.size
-    send(0, L0, Aidx)
+    C = D = E = 0
+    U = int(Aidx.size)
+    maxI = 0
+    dd, ee = send(0, ring[0], Aidx)
+    D += dd
+    E += ee
+    rows = []
     T = -1
     t = 0
-    last_arrival = max(arrivals) if arrivals else 0
     while t < t_limit:
         t += 1
-        if t > last_arrival:
+        if not arrive[t:].any():
+            t -= 1
             break
-        Lt = hist[-1].copy()
-        # every edge's contribution: L_{t-f1}(u) - f2 for t - f1 >= 0
-        for f in range(1, fmax + 1):
-            if t - f < 0:
-                break
-            sel = a1 == f
-            if not sel.any():
-                continue
-            val = hist[t - f][src[sel]] - a2[sel]
-            np.maximum.at(Lt, dst[sel], val)
-        Lt = np.maximum(Lt, 0)
+        prev = ring[(t - 1) % W]
+        Lt = prev.copy()
+        for (dst, src, a1, a2) in slots:
+            ok = a1 <= t
+            if not ok.all():
+                dst, src, a1, a2 = dst[ok], src[ok], a1[ok], a2[ok]
+            val = ring[(t - a1) % W, src] - a2
+            Lt[dst] = np.maximum(Lt[dst], val)
         Lt[Aidx] = M
-        improved = np.nonzero(Lt > hist[-1])[0]
-        hist.append(Lt)
-        if arrivals.get(t, 0) > 0:
+        improved = np.nonzero(Lt > prev)[0]
+        ring[t % W] = Lt
+        delivered = int(arrive[t]) if t < arrive.size else 0
+        if delivered:
             C += 1
-        U += improved.size
-        maxI = max(maxI, improved.size)
-        if (Bm[improved]).any():
+        U += int(improved.size)
+        maxI = max(maxI, int(improved.size))
+        if Bm[improved].any():
             T = t
+            if delivered:
+                rows.append([t, delivered, int(improved.size), 0])
             break
-        send(t, Lt, improved)
-        if arrivals:
-            last_arrival = max(last_arrival, max(arrivals))
-    horizon = T if T >= 0 else len(hist) - 1
-    R = sum(c for ta, c in arrivals.items() if ta <= horizon)
-    # flows in transit right after each sending round s: sent at <= s, arriving > s
-    send_rounds = sorted({0} | {ta for ta in arrivals if ta < horizon or T < 0})
-    sent_arr = np.array(sent_log, dtype=np.int64).reshape(-1, 2)
-    P = 0
-    for s in send_rounds:
-        if s > horizon or (T >= 0 and s >= T):
-            continue
-        k = int(((sent_arr[:, 0] <= s) & (sent_arr[:, 1] > s)).sum())
-        P = max(P, k)
-    out = dict(T=T, labels=hist[horizon].copy(),
-               counters=dict(C=C, U=U, D=D, E=E, R=R, P=P, I=maxI))
+        dd, ee = send(t, Lt, improved)
+        D += dd
+        E += ee
+        if delivered:
+            rows.append([t, delivered, int(improved.size), ee])
+    horizon = t
+    R = int(arrive[1:horizon + 1].sum())
+    # in transit after each sending round s (s = 0 and the cycle times before
+    # T): sent at or before s, arriving after s
+    tl = max(arrive.size, sent.size)
+    cs = np.cumsum(grow(sent, tl)[:tl])
+    ca = np.cumsum(grow(arrive, tl)[:tl])
+    rounds = [0] + [r[0] for r in rows if T < 0 or r[0] < T]
+    P = max(int(cs[s] - ca[s]) for s in rounds)
+    out = dict(T=T, labels=ring[horizon % W].copy(),
+               counters=dict(C=C, U=U, D=D, E=E, R=R, P=P, I=maxI),
+               rows=np.array(rows, dtype=np.int64).reshape(-1, 4))
     if T < 0:
         out.update(X=-1, x=-1, Y=-1, F2=-1)
         return out
-    adj = adjacency(nv, edges)
-
-    def Lfun(tt, v):
-        return int(hist[tt][v])
-
-    X, x, Y, F2 = _pick_outputs(adj, Lfun, Bm, T, M)
-    out.update(X=X, x=x, Y=Y, F2=F2)
+    LT = ring[T % W]
+    Bidx = np.nonzero(Bm & (LT > 0))[0]
+    X = int(Bidx[np.argmax(LT[Bidx])])               # first maximum = smallest index
+    LX = int(LT[X])
+    # neighbours of X in ascending order: the first that delivers LX at T
+    sel = (osrc == X)
+    nb = sorted(zip(odst[sel].tolist(), oa1[sel].tolist(), oa2[sel].tolist(),
+                    np.concatenate([ids, ids])[order][sel].tolist()))
+    Y = x = None
+    for (y, a, b, e) in nb:
+        if T - a >= 0 and int(ring[(T - a) % W, y]) - b == LX:
+            Y, x = y, e
+            break
+    out.update(X=X, x=int(x), Y=int(Y), F2=M - LX)
     return out
 
 

@@ -175,10 +175,38 @@ def test_square64_vs_recurrence(seed):
     inst = gen.square64(seed)
     edges = pins.lattice_edge_list(inst.d, inst.n, inst.f1, inst.f2)
     ref = pins.dp_solve(inst.N, edges, inst.A, inst.B, inst.M)
-    r = O.solve_instance(inst)
+    r = O.solve_instance(inst, trace_cap=100000)
     _check_tuple(r, ref["T"], ref["X"], ref["x"], ref["Y"], ref["F2"])
     assert np.array_equal(r.labels.astype(np.int64), ref["labels"])
     assert r.counters == ref["counters"]
+    assert np.array_equal(r.trace, ref["rows"])
+
+
+@pytest.mark.parametrize("case", DP_CASES)
+def test_trace_rows_vs_recurrence(case):
+    """Every row of the oracle's cycle trace (t, delivered, |I_t|, sent)
+    equals the one the recurrence enumerates."""
+    d, n, seed, K1, K2, M = case
+    inst = _inst(d, n, seed, K1, K2, M)
+    edges = pins.lattice_edge_list(d, n, inst.f1, inst.f2)
+    ref = pins.dp_solve(inst.N, edges, inst.A, inst.B, M)
+    r = O.solve_instance(inst, trace_cap=100000)
+    assert r.trace.shape == ref["rows"].shape
+    assert np.array_equal(r.trace, ref["rows"])
+
+
+def test_cube128_golden_vs_recurrence():
+    """The stored oracle output for the 128^3 cube (seed 13, M = 1000) against
+    the recurrence run on the full lattice: T, X, x, Y, F2, every counter and
+    the SHA-256 of all 2,097,152 labels."""
+    import hashlib
+    g = json.load(open(os.path.join(GOLDEN, "cube128_s13_M1000.json")))
+    inst = gen.cube128(13, 1000)
+    edges = pins.lattice_edge_list(inst.d, inst.n, inst.f1, inst.f2)
+    ref = pins.dp_solve(inst.N, edges, inst.A, inst.B, inst.M)
+    assert (ref["T"], ref["X"], ref["x"], ref["Y"], ref["F2"]) == (g["T"], g["X"], g["x"], g["Y"], g["F2"])
+    assert ref["counters"] == g["counters"]
+    assert hashlib.sha256(ref["labels"].astype("<u4").tobytes()).hexdigest() == g["labels_sha256"]
 
 
 # ---------------------------------------------------------------------------
@@ -257,7 +285,15 @@ def test_labels_never_decrease_over_cycles():
     t = full.trace[:, 0]
     assert len(t) == full.counters["C"] and np.all(np.diff(t) > 0) and t[-1] == full.T
     assert full.trace[:, 1].sum() == full.counters["R"]
-    assert full.trace[:, 3].sum() + 0 <= full.counters["E"]
+    assert full.trace[:, 2].sum() + int(inst.A.sum()) == full.counters["U"]
+    # every flow is sent either from A at t = 0 or from a row's I_t: A sends
+    # over each edge to a vertex outside A (label 0) whose weight is below M
+    edges = pins.lattice_edge_list(inst.d, inst.n, inst.f1, inst.f2)
+    us, vs, _w1, w2, _ids = edges
+    a = inst.A.astype(bool)
+    sent0 = int(((a[us] & ~a[vs] & (w2 < inst.M)) | (a[vs] & ~a[us] & (w2 < inst.M))).sum())
+    assert full.trace[:, 3].sum() + sent0 == full.counters["E"]
+    assert full.trace[-1, 3] == 0
 
 
 @pytest.mark.parametrize("case", [(2, 12, 1, 5, 5, 50), (3, 6, 3, 10, 10, 60), (2, 64, 2, 5, 5, 200)])
