@@ -108,19 +108,19 @@ int csp_solve(csp_ctx *ctx, int d, int64_t n,
  * path gives *len = 0.  Inputs are device pointers as for csp_solve_dev.
  * `scratch_mask` is a caller-owned device uint8 [N] used for B'; it must be
  * all zero on entry and is all zero again on return. */
-/* Same on host buffers (inputs as for csp_solve; the B' mask lives in ctx).
- * Synchronous. */
-int csp_reconstruct(csp_ctx *ctx, int d, int64_t n,
-                    const uint8_t *f1, const uint8_t *f2,
-                    const uint8_t *A, const uint8_t *B, uint32_t M,
-                    int64_t *path, int64_t cap, int64_t *len, csp_result *out);
-
 int csp_reconstruct_dev(csp_ctx *ctx, int d, int64_t n,
                         const uint8_t *f1, const uint8_t *f2,
                         const uint8_t *A, const uint8_t *B, uint32_t M,
                         uint8_t *scratch_mask,
                         int64_t *path, int64_t cap, int64_t *len,
                         csp_result *out, void *stream);
+
+/* Same on host buffers (inputs as for csp_solve; the B' mask lives in ctx).
+ * Synchronous. */
+int csp_reconstruct(csp_ctx *ctx, int d, int64_t n,
+                    const uint8_t *f1, const uint8_t *f2,
+                    const uint8_t *A, const uint8_t *B, uint32_t M,
+                    int64_t *path, int64_t cap, int64_t *len, csp_result *out);
 
 /* The same cycle on a general graph (section 1 states the problem for any
  * graph with positive integer f1, f2; the lattice is the case the paper
@@ -236,6 +236,24 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
                  const uint8_t *B, uint32_t M, int *blocks, int *path, float *ms, void *stream);
 int csp_autotune_clear(csp_ctx *ctx);
 
+/* Dense/sparse form of the improved set I_t (section 6, Step 8 condenses
+ * the triggered vertices into one list).  Each workgroup of the
+ * range-owned kernel collects the vertices of its range whose label rose
+ * at t, first as an unordered list appended during the deliveries (sparse
+ * form); when that list holds more than `vertices` entries the workgroup
+ * sweeps its improved-vertex bitmap into a list in vertex order (dense
+ * form), so that neighbouring vertices' edge records are read together in
+ * the sending step.  0 sweeps every cycle; a value of 2^32 - 1 or more
+ * never sweeps; -1 (the default) restores the automatic choice (the
+ * autotuned value for the lattice shape, else the library's default).
+ * Changes speed, never results.  csp_autotune tries, on the configuration
+ * it chose, the thresholds never, 0, 256, 1024 and 4096 and records the
+ * fastest (when at least 3 % faster than the automatic one);
+ * csp_tuned_dense_threshold reports what it recorded for a shape (-1:
+ * nothing, the automatic choice applies). */
+int csp_set_dense_threshold(csp_ctx *ctx, int64_t vertices);
+int csp_tuned_dense_threshold(const csp_ctx *ctx, int d, int64_t n, int64_t *vertices);
+
 /* Cycle trace for later csp_solve_dev calls on ctx (off when cap = 0):
  * trace is a device buffer of cap rows of four int64, one row per time at
  * which water is delivered (section 4, Algorithm 1's loop): t, flows
@@ -248,7 +266,7 @@ int csp_autotune_clear(csp_ctx *ctx);
 int csp_set_trace(csp_ctx *ctx, int64_t *trace, int64_t cap);
 int csp_last_trace_rows(const csp_ctx *ctx, int64_t *rows);
 
-/* Phase timing of the cycle kernel (off by default).  When on, workgroup 0
+/* Phase timing of the cycle kernel (off by default; on = 1 or 2).  When on, workgroup 0
  * accumulates wall-clock time per phase; csp_last_phase_us fills us[6] with
  * microseconds spent in: departure work, the barrier after it, finding the
  * next time, arrival work, the barrier after it, and the frontier gather,
@@ -258,13 +276,25 @@ int csp_last_trace_rows(const csp_ctx *ctx, int64_t *rows);
 int csp_set_phase_timing(csp_ctx *ctx, int on);
 int csp_last_phase_us(const csp_ctx *ctx, double *us);
 
+/* Phase timing over every workgroup of the range-owned kernel: with
+ * csp_set_phase_timing(ctx, 2) each workgroup times its own phases, and
+ * after a solve mean[6] and max[6] receive, per phase, the mean over the
+ * workgroups and the largest single workgroup's total, in microseconds:
+ * slot 0 the sending step (Steps 4-5 inside the range), 1 publishing at
+ * the barrier (release fence, counting in, and the combine for the last
+ * to arrive), 4 waiting for the barrier's release, 2 testing the
+ * candidates other ranges shipped, 3 the deliveries (Steps 1-3, 8) and
+ * building I_t.  Zero when the last solve took the global-label kernel. */
+int csp_last_phase_spread(const csp_ctx *ctx, double *mean, double *max);
+
 /* ---- Serving: continuous batching of solves and reconstructions --------
  *
  * A server runs one persistent kernel whose workers (one workgroup per CU)
  * keep taking work while it runs: requests submitted while others are on
  * the GPU are admitted as soon as job slots, workers and arena memory free
  * up, in submission order, and run beside them.  A request is one solve
- * (sections 4-6) and, when asked, the path reconstruction of section 2
+ * (sections 4-6) and, when asked, the path reconstruction of section 1 and
+ * section 5 "Termination"
  * (repeated solves with B' = {Y}, M' = F2 - f2(x) + 1 until Y is in A),
  * carried out by the same workers on device-resident state.  Results are
  * identical to csp_solve_dev / csp_reconstruct_dev on the request alone.

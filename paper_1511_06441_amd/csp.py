@@ -30,6 +30,7 @@ EXPORTED = (
     "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
     "csp_reconstruct_log_dev", "csp_solve_graph_dev", "csp_autotune", "csp_autotune_clear",
     "csp_set_batch_target", "csp_autotune_batch", "csp_reconstruct",
+    "csp_set_dense_threshold", "csp_tuned_dense_threshold", "csp_last_phase_spread",
 )
 
 
@@ -124,6 +125,12 @@ def _load():
     lib.csp_set_trace.restype = i32
     lib.csp_last_trace_rows.argtypes = [p, ctypes.POINTER(i64)]
     lib.csp_last_trace_rows.restype = i32
+    lib.csp_last_phase_spread.argtypes = [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.csp_last_phase_spread.restype = i32
+    lib.csp_set_dense_threshold.argtypes = [p, i64]
+    lib.csp_set_dense_threshold.restype = i32
+    lib.csp_tuned_dense_threshold.argtypes = [p, i32, i64, ctypes.POINTER(i64)]
+    lib.csp_tuned_dense_threshold.restype = i32
     lib.csp_serve_open.argtypes = [p, ctypes.c_uint64, i32, ctypes.POINTER(p)]
     lib.csp_serve_open.restype = i32
     lib.csp_serve_submit.argtypes = [p, ctypes.POINTER(csp_request)]
@@ -279,6 +286,16 @@ def csp_autotune(ctx, d, n, f1, f2, A, B, M, stream=None):
     return b.value, pth.value, ms.value
 
 
+def csp_set_dense_threshold(ctx, vertices: int):
+    _check(ctx, lib.csp_set_dense_threshold(ctx, vertices))
+
+
+def csp_tuned_dense_threshold(ctx, d: int, n: int) -> int:
+    v = ctypes.c_int64()
+    _check(ctx, lib.csp_tuned_dense_threshold(ctx, d, n, ctypes.byref(v)))
+    return v.value
+
+
 def csp_autotune_clear(ctx):
     _check(ctx, lib.csp_autotune_clear(ctx))
 
@@ -301,8 +318,9 @@ PHASES = ("departure", "barrier_after_departure", "next_time", "arrival",
           "barrier_after_arrival", "frontier_gather")
 
 
-def csp_set_phase_timing(ctx, on: bool):
-    _check(ctx, lib.csp_set_phase_timing(ctx, 1 if on else 0))
+def csp_set_phase_timing(ctx, on):
+    """False/0 off, True/1 workgroup 0, 2 every workgroup (csp_last_phase_spread)."""
+    _check(ctx, lib.csp_set_phase_timing(ctx, int(on)))
 
 
 def csp_reconstruct_log_dev(ctx, d, n, f1, f2, A, B, M, cap, stream=None):
@@ -366,6 +384,18 @@ def csp_last_phase_us(ctx) -> dict:
     us = (ctypes.c_double * 6)()
     _check(ctx, lib.csp_last_phase_us(ctx, us))
     return dict(zip(PHASES, list(us)))
+
+
+SPREAD_PHASES = ("send", "publish", "candidates", "deliver", "wait")
+
+
+def csp_last_phase_spread(ctx) -> dict:
+    """Per phase of the range-owned kernel: (mean over workgroups, largest
+    workgroup) in microseconds, after a solve with phase timing 2."""
+    mean, mx = (ctypes.c_double * 6)(), (ctypes.c_double * 6)()
+    _check(ctx, lib.csp_last_phase_spread(ctx, mean, mx))
+    slots = {"send": 0, "publish": 1, "candidates": 2, "deliver": 3, "wait": 4}
+    return {k: (mean[i], mx[i]) for k, i in slots.items()}
 
 
 # --- convenience ------------------------------------------------------------

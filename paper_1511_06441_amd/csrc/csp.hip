@@ -40,7 +40,7 @@
 //
 // k_batch runs many range-owned solves in one persistent launch (a gang of
 // workgroups per problem) and k_serve keeps such workers alive while a host
-// feeds them requests, including the reconstruction chain of section 2.
+// feeds them requests, including the reconstruction chain of section 1 and section 5 ("Termination").
 //
 // Measured on MI355X, and the reason for the shapes above: device atomics on
 // one address serialise at ~11 ns each; scattered atomicMax reaches ~27 G/s;
@@ -85,6 +85,8 @@ struct Out {
     long long res[5];              // T X x Y F2
     unsigned long long ctr[8];     // C U D E R P I
     unsigned long long prof[8];    // wall-clock ticks per phase (range 0)
+    unsigned long long psum[8];    // per-phase ticks summed over ranges (phase timing 2)
+    unsigned long long pmax[8];    // per-phase ticks, largest range (phase timing 2)
     long long trace_rows;          // cycle rows produced (may exceed the trace capacity)
     long long xrec;                // improvement record of X at T (logging runs)
     int status;
@@ -741,6 +743,7 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
 // ===========================================================================
 
 constexpr int KMAX = 4;                 // neighbours lie within KMAX ranges
+constexpr unsigned DENSE_NEVER = 0xFFFFFFFFu;   // dense threshold: keep the append list
 constexpr int NOMAX = 2 * KMAX + 1;
 
 // What a gang barrier combines.  mn is below 0xFFFF or 0xFFFFFFFF (none);
@@ -798,7 +801,7 @@ __device__ __forceinline__ void comb_wave(unsigned &mn, unsigned &orf, unsigned 
 // wait that outlasts `limit` wall-clock ticks marks the gang broken and the
 // call returns false, so a logic error drains the gang instead of hanging.
 __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
-                             const Comb &mine, Comb &out, bool need_rest)
+                             const Comb &mine, Comb &out, bool need_rest, unsigned long long *tpub = nullptr)
 {
     __shared__ int s_ok;
     __shared__ unsigned long long s_o[5];
@@ -895,6 +898,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
             int ok = 1;
             unsigned long long *fl = bar_flag(bh, g, m);
             const unsigned long long t0 = wall_clock64();
+            if (tpub) *tpub = t0;           // published (and combined, if the last): the wait starts
             unsigned long long w;
             while (((w = ld64(&fl[0])) >> 32) < (unsigned long long)epoch) {
                 __builtin_amdgcn_s_sleep(1);
@@ -946,6 +950,7 @@ struct RJ {
     int K;                         // neighbours lie within K ranges
     int lt;                        // LDS label bytes (2 or 4)
     int llist;                     // frontier list entries kept in LDS (16-bit local indices); the rest in lists
+    unsigned dense_thr;            // a range whose I_t is larger sweeps its bitmap into an index-ordered list
     int tile;                      // 1 (d = 3): ranges are x-pencils of n x ty x tz vertices
     int ty, tz;                    // pencil extent along y and z
     unsigned nty;                  // pencils along y
@@ -1152,7 +1157,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     __shared__ unsigned long long s_lc[7];
     if (tid < 7) s_lc[tid] = 0;
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
-    const bool timing = p.prof && lead && tid == 0;
+    // phase timing 1: range 0 only; 2: every range (sums and maxima)
+    const bool timing = tid == 0 && (p.prof == 2 || (p.prof && lead));
+    __shared__ unsigned long long s_tpub;
 #define PHASE4(k)                                            \
     do {                                                     \
         if (timing) {                                        \
@@ -1308,6 +1315,37 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         if (lane == 0 && bestB) {
             atomicMax(&s_xkey, bestB);
             atomicOr(&s_flags, SF_BHIT);
+        }
+        __syncthreads();
+        return total;
+    };
+
+    // Dense form of I_t (Step 8's condensed list in vertex order): sweep the
+    // frontier bitmap, two words per thread, into the list in ascending
+    // local index, so that the departure's lanes read the edge records of
+    // neighbouring vertices together.  The bitmap is left as it is (the
+    // departure clears it).
+    auto sweep = [=]() -> unsigned {
+        unsigned total = 0;
+        for (unsigned w0 = 0; w0 < cw; w0 += 2 * BLOCK) {
+            const unsigned wi = w0 + 2 * tid;
+            const unsigned b0 = wi < cw ? fb[wi] : 0u, b1 = wi + 1 < cw ? fb[wi + 1] : 0u;
+            unsigned tot;
+            const unsigned ex = block_scan((unsigned)(__popc(b0) + __popc(b1)), s_wave, &tot);
+            unsigned k = total + ex;
+            unsigned bits = b0;
+            while (bits) {
+                const unsigned bt = (unsigned)(__ffs(bits) - 1);
+                bits &= bits - 1u;
+                list_put(k++, wi * 32u + bt);
+            }
+            bits = b1;
+            while (bits) {
+                const unsigned bt = (unsigned)(__ffs(bits) - 1);
+                bits &= bits - 1u;
+                list_put(k++, (wi + 1) * 32u + bt);
+            }
+            total += tot;
         }
         __syncthreads();
         return total;
@@ -1511,8 +1549,17 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         mine.s1 = nlist;
         mine.s2 = transit;
         mine.mx = s_xkey;
-        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false)) { status = ST_BROKEN; break; }
-        PHASE4(1);
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false, p.prof ? &s_tpub : nullptr)) {
+            status = ST_BROKEN;
+            break;
+        }
+        if (timing) {
+            // publish (release fence, counting, the combine when last) and wait
+            const unsigned long long now_ = wall_clock64();
+            ph[1] += s_tpub - ph_t;
+            ph[4] += now_ - s_tpub;
+            ph_t = now_;
+        }
 
         if (all.orf & SF_OVER) { status = ST_OVERFLOW; break; }
         if (cyc > 0 && lead && tid == 0) {
@@ -1739,6 +1786,8 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                     atomicOr(&s_flags, SF_BHIT);
                 }
             }
+            // a large I_t is rebuilt in vertex order (the same set)
+            if (nlist > p.dense_thr) nlist = sweep();
             if (tid == 0) {
                 cnt[bk] = 0;
                 cU += nlist;
@@ -1773,6 +1822,12 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         if (s_red[1]) atomicAdd(&out->ctr[2], s_red[1]);
         if (s_red[2]) atomicAdd(&out->ctr[3], s_red[2]);
         if (s_red[3]) atomicAdd(&out->ctr[4], s_red[3]);
+        if (p.prof == 2) {
+            for (int i = 0; i < 6; ++i) {
+                atomicAdd(&out->psum[i], ph[i]);
+                atomicMax(&out->pmax[i], ph[i]);
+            }
+        }
         if (lead) {
             for (int i = 0; i < 6; ++i) out->prof[i] = ph[i];
             out->ctr[0] = s_lc[0];
@@ -1868,7 +1923,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a)
 // idle worker at a time (the watcher) reads the host's tail and mirrors it
 // into device memory, so idle workers spin on L2 rather than on the bus.
 // A job is the solve of its range, then, when asked, the reconstruction
-// chain of section 2 (re-solve with B' = {Y} and M' = F2 - f2(x) + 1 until
+// chain of section 1 and section 5 "Termination" (re-solve with B' = {Y} and M' = F2 - f2(x) + 1 until
 // Y is in A), run by the same gang with the lattice still resident.  The
 // last member to finish writes the completion record to host memory.
 // Workers leave when the host raises stop, or when the host has not beaten
@@ -2492,6 +2547,12 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
         if (s_red[1]) atomicAdd(&out->ctr[2], s_red[1]);
         if (s_red[2]) atomicAdd(&out->ctr[3], s_red[2]);
         if (s_red[3]) atomicAdd(&out->ctr[4], s_red[3]);
+        if (p.prof == 2) {
+            for (int i = 0; i < 6; ++i) {
+                atomicAdd(&out->psum[i], ph[i]);
+                atomicMax(&out->pmax[i], ph[i]);
+            }
+        }
         if (lead) {
             for (int i = 0; i < 6; ++i) out->prof[i] = ph[i];
             out->ctr[0] = s_lc[0];
@@ -2572,6 +2633,9 @@ struct csp_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_ms = -1.f;
     unsigned long long last_prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long last_psum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long last_pmax[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long long last_spread_ranges = 0;
     int prof = 0;
     unsigned long long pool_hint = 0;
     int blocks_override = 0;
@@ -2582,7 +2646,9 @@ struct csp_ctx {
         long long N;
         int blocks, path;
         float ms;
+        long long dense;            // dense threshold (-1: automatic)
     };
+    long long dense_override = -1;  // -1 automatic, else the threshold for later solves
     std::vector<Tuned> tuned;
     long long batch_target = 0;     // batch: vertices per workgroup (0 = fewest workgroups)
     // batch: wheel pool and candidate capacity a problem (same lattice, masks
@@ -2832,6 +2898,26 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
     return pl;
 }
 
+// Automatic dense threshold of a range of c vertices.
+unsigned dense_default(long long c)
+{
+    (void)c;
+    return DENSE_NEVER;
+}
+
+// Dense threshold of a single solve: the override, else the autotuned one,
+// else automatic.
+unsigned dense_for(const csp_ctx *ctx, int d, long long N, long long c)
+{
+    long long v = ctx->dense_override;
+    if (v < 0) {
+        const csp_ctx::Tuned *e = tuned_for(ctx, d, N);
+        v = e ? e->dense : -1;
+    }
+    if (v < 0) return dense_default(c);
+    return v >= (long long)DENSE_NEVER ? DENSE_NEVER : (unsigned)v;
+}
+
 void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const uint8_t *f1, const uint8_t *f2, const uint8_t *A, const uint8_t *B, uint32_t M)
 {
     memset(&p, 0, sizeof(p));
@@ -2842,6 +2928,7 @@ void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const
     p.K = plan.K;
     p.lt = plan.lt;
     p.llist = plan.llist;
+    p.dense_thr = dense_default(plan.c);
     p.tile = plan.tile;
     p.ty = plan.ty;
     p.tz = plan.tz;
@@ -3039,6 +3126,9 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
     if (log && !use_lds) return fail(ctx, CSP_EINVAL, "the improvement log needs the range-owned kernel");
     // log records per range: at least two per vertex, else what a solve needed before
     unsigned long long log_cap = log ? std::max<unsigned long long>(2ull * plan.c, ctx->log_seen) : 0ull;
+    // record indices are 32-bit across all G ranges: a size remembered from a
+    // solve with fewer ranges may not fit this one
+    if (log) log_cap = std::min<unsigned long long>(log_cap, ((1ull << 32) - 1) / (unsigned long long)G);
     ctx->last_path = use_lds ? 1 : 2;
 
     // wheel capacity: start from the largest a solve has needed, at least
@@ -3086,6 +3176,7 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
             }
             RJ p;
             fill_job(p, d, n, N, plan, f1, f2, A, B, M);
+            p.dense_thr = dense_for(ctx, d, N, plan.c);
             p.rec = ctx->rec;
             p.lists = ctx->queue;
             p.pool = ctx->pool;
@@ -3182,7 +3273,12 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
             ctx->cand_seen = std::max(ctx->cand_seen, ccap);
         }
         HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
-        for (int i = 0; i < 8; ++i) ctx->last_prof[i] = prof[i];
+        for (int i = 0; i < 8; ++i) {
+            ctx->last_prof[i] = prof[i];
+            ctx->last_psum[i] = use_lds && ctx->prof == 2 ? c.rout.psum[i] : 0;
+            ctx->last_pmax[i] = use_lds && ctx->prof == 2 ? c.rout.pmax[i] : 0;
+        }
+        ctx->last_spread_ranges = use_lds ? G : 0;
         ctx->last_trace_rows = use_lds ? c.rout.trace_rows : 0;
         ctx->last_xrec = log ? c.rout.xrec : -1;
         if (log && !ctx->pool_hint) ctx->log_seen = std::max(ctx->log_seen, log_cap);
@@ -3472,8 +3568,19 @@ int csp_set_pool_hint(csp_ctx *ctx, uint64_t flows_per_bucket)
 
 int csp_set_phase_timing(csp_ctx *ctx, int on)
 {
-    if (!ctx) return CSP_EINVAL;
-    ctx->prof = on ? 1 : 0;
+    if (!ctx || on < 0 || on > 2) return CSP_EINVAL;
+    ctx->prof = on;
+    return CSP_OK;
+}
+
+int csp_last_phase_spread(const csp_ctx *ctx, double *mean, double *mx)
+{
+    if (!ctx || !mean || !mx) return CSP_EINVAL;
+    const double G = ctx->last_spread_ranges > 0 ? (double)ctx->last_spread_ranges : 1.0;
+    for (int i = 0; i < 6; ++i) {
+        mean[i] = (double)ctx->last_psum[i] * 1000.0 / (double)ctx->wall_khz / G;
+        mx[i] = (double)ctx->last_pmax[i] * 1000.0 / (double)ctx->wall_khz;
+    }
     return CSP_OK;
 }
 
@@ -4287,7 +4394,9 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
     csp_result r0, r1;
     csp_counters c0, c1;
     bool have = false;
-    csp_ctx::Tuned best{d, N, b0, 0, 0.f}, base = best;
+    csp_ctx::Tuned best{d, N, b0, 0, 0.f, -1}, base = best;
+    const long long save_dense = ctx->dense_override;
+    ctx->dense_override = -1;
     for (int pth : ps) {
         for (int b : bs) {
             ctx->blocks_override = b;
@@ -4304,30 +4413,79 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
             if (rc) {
                 ctx->blocks_override = save_b;
                 ctx->path_override = save_p;
+                ctx->dense_override = save_dense;
                 return rc;
             }
             if (!have) {
                 r0 = r1;
                 c0 = c1;
                 have = true;
-                base = csp_ctx::Tuned{d, N, b, pth, t};      // the automatic configuration
+                base = csp_ctx::Tuned{d, N, b, pth, t, -1};  // the automatic configuration
             } else if (memcmp(&r0, &r1, sizeof(r0)) != 0 || memcmp(&c0, &c1, sizeof(c0)) != 0) {
                 ctx->blocks_override = save_b;
                 ctx->path_override = save_p;
+                ctx->dense_override = save_dense;
                 return fail(ctx, CSP_EDEVICE, "autotune: two configurations gave different results");
             }
-            if (best.ms <= 0.f || t < best.ms) best = csp_ctx::Tuned{d, N, b, pth, t};
+            if (best.ms <= 0.f || t < best.ms) best = csp_ctx::Tuned{d, N, b, pth, t, -1};
+        }
+    }
+    // another configuration replaces the automatic one only when it is at
+    // least 3 % faster, so that timing noise does not pick it
+    if (best.ms > 0.97f * base.ms) best = base;
+    // then the dense threshold on the chosen shape: sizes of I_t per range
+    // above which it is swept into vertex order (never, always, and between)
+    {
+        ctx->blocks_override = best.blocks;
+        ctx->path_override = best.path;
+        const csp_ctx::Tuned shape = best;
+        for (long long thr : {(long long)DENSE_NEVER, 0ll, 256ll, 1024ll, 4096ll}) {
+            ctx->dense_override = thr;
+            float t = -1.f;
+            for (int rep = 0; rep < 2 && rc == CSP_OK; ++rep) {
+                rc = solve_impl(ctx, d, n, f1, f2, A, B, M, nullptr, &r1, &c1, 0, stream, false);
+                if (rc == CSP_OK && (t < 0.f || ctx->last_ms < t)) t = ctx->last_ms;
+            }
+            if (rc == CSP_OK && (memcmp(&r0, &r1, sizeof(r0)) != 0 || memcmp(&c0, &c1, sizeof(c0)) != 0))
+                rc = fail(ctx, CSP_EDEVICE, "autotune: two dense thresholds gave different results");
+            if (rc) {
+                ctx->blocks_override = save_b;
+                ctx->path_override = save_p;
+                ctx->dense_override = save_dense;
+                return rc;
+            }
+            if (ctx->last_path != 1) break;         // global-label kernel: no ranges to sweep
+            if (t < 0.97f * best.ms) {
+                best = shape;
+                best.dense = thr;
+                best.ms = t;
+            }
         }
     }
     ctx->blocks_override = save_b;
     ctx->path_override = save_p;
-    // another configuration replaces the automatic one only when it is at
-    // least 3 % faster, so that timing noise does not pick it
-    if (best.ms > 0.97f * base.ms) best = base;
+    ctx->dense_override = save_dense;
     ctx->tuned.push_back(best);
     if (blocks) *blocks = best.blocks;
     if (path) *path = best.path;
     if (ms) *ms = best.ms;
+    return CSP_OK;
+}
+
+int csp_set_dense_threshold(csp_ctx *ctx, int64_t vertices)
+{
+    if (!ctx) return CSP_EINVAL;
+    ctx->dense_override = vertices < 0 ? -1 : vertices;
+    return CSP_OK;
+}
+
+int csp_tuned_dense_threshold(const csp_ctx *ctx, int d, int64_t n, int64_t *vertices)
+{
+    if (!ctx || !vertices || d < 1 || d > 4 || n < 2) return CSP_EINVAL;
+    long long N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    const csp_ctx::Tuned *e = tuned_for(ctx, d, N);
+    *vertices = e ? e->dense : -1;
     return CSP_OK;
 }
 

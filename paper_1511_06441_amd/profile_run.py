@@ -25,6 +25,9 @@ def main():
                     choices=["cube128", "cube128set", "cube256", "cube256stress", "square64"])
     ap.add_argument("--M", type=int, default=700)
     ap.add_argument("--solves", type=int, default=3)
+    ap.add_argument("--dense", type=int, default=-1,
+                    help="dense threshold of the improved set (-1 automatic, 0 always, 4294967295 never)")
+    ap.add_argument("--phases", action="store_true", help="also print the per-phase time of each solve")
     args = ap.parse_args()
 
     import torch
@@ -45,12 +48,20 @@ def main():
              "cube256stress": lambda: [gen.cube256_stress(22)],
              "square64": lambda: [gen.square64(1)]}[args.workload]()
     s = csp.Solver(0)
+    csp.csp_set_dense_threshold(s.ctx, args.dense)
+    if args.phases:
+        csp.csp_set_phase_timing(s.ctx, 2)
     for inst in insts:
         di = csp.to_device(inst)
         for i in range(args.solves):
             res, cnt = s.solve(di)
             print(f"{inst.name} solve {i}: {res.tuple()} C={cnt.C} R={cnt.R} "
                   f"kernel_ms={csp.csp_last_kernel_ms(s.ctx):.3f}", flush=True)
+            if args.phases:
+                sp = csp.csp_last_phase_spread(s.ctx)
+                C = max(cnt.C, 1)
+                print("  phases, us per cycle (mean over workgroups / largest workgroup): " +
+                      " ".join(f"{k}={a / C:.2f}/{b / C:.2f}" for k, (a, b) in sp.items()), flush=True)
     s.close()
 
 

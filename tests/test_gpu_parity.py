@@ -44,18 +44,20 @@ def solver(torch):
 PATHS = [1, 2, 3]       # range-owned, global labels, range-owned with pencils for d = 3
 
 
-def gpu_solve(solver, torch, inst, blocks=0, path=0, **kw):
+def gpu_solve(solver, torch, inst, blocks=0, path=0, dense=-1, **kw):
     from paper_1511_06441_amd import csp
     di = csp.to_device(inst)
     lab = torch.zeros(inst.N, dtype=torch.int32, device="cuda")
     csp.csp_set_blocks(solver.ctx, blocks)
     csp.csp_set_path(solver.ctx, path)
+    csp.csp_set_dense_threshold(solver.ctx, dense)
     try:
         res, cnt = solver.solve(di, labels=lab, **kw)
         used = csp.csp_last_path(solver.ctx)
     finally:
         csp.csp_set_blocks(solver.ctx, 0)
         csp.csp_set_path(solver.ctx, 0)
+        csp.csp_set_dense_threshold(solver.ctx, -1)
     torch.cuda.synchronize()
     _say("  path", used, "kernel_ms %.3f" % csp.csp_last_kernel_ms(solver.ctx))
     assert path == 0 or used == (1 if path == 3 else path)
@@ -117,6 +119,24 @@ def test_small_vs_oracle(solver, torch, case, path):
     _say("case", inst.name, "path", path)
     ref = _oracle(inst)
     res, cnt, lab = gpu_solve(solver, torch, inst, path=path)
+    _compare(inst, res, cnt, lab, ref)
+
+
+# dense form of I_t: 0 sweeps the bitmap every cycle, 2^32-1 never does,
+# 64 switches between the two forms from cycle to cycle
+DENSE = [0, 64, 0xFFFFFFFF]
+
+
+@pytest.mark.parametrize("dense", DENSE)
+@pytest.mark.parametrize("path", [1, 3])
+@pytest.mark.parametrize("case", SMALL, ids=[f"d{c[0]}n{c[1]}s{c[2]}M{c[5]}" for c in SMALL])
+def test_dense_sweep_vs_oracle(solver, torch, case, path, dense):
+    d, n, seed, K1, K2, M, c1, c2 = case
+    inst = gen.opposite_faces(d, n, seed, K1, K2, M, f1_const=c1, f2_const=c2)
+    inst.name = f"d{d}n{n}s{seed}M{M}"
+    _say("case", inst.name, "path", path, "dense", dense)
+    ref = _oracle(inst)
+    res, cnt, lab = gpu_solve(solver, torch, inst, path=path, dense=dense, blocks=8)
     _compare(inst, res, cnt, lab, ref)
 
 
@@ -214,6 +234,21 @@ def test_full_size_vs_stored_oracle(solver, torch, name, path):
     inst = _build(rec)
     _say("case", name, "path", path)
     res, cnt, lab = gpu_solve(solver, torch, inst, path=path)
+    assert res.tuple() == (rec["T"], rec["X"], rec["x"], rec["Y"], rec["F2"])
+    assert cnt.asdict() == rec["counters"]
+    assert hashlib.sha256(lab.astype("<u4").tobytes()).hexdigest() == rec["labels_sha256"]
+
+
+@pytest.mark.parametrize("dense", [0, 1024])
+@pytest.mark.parametrize("name", _golden_cases())
+def test_full_size_dense_vs_stored_oracle(solver, torch, name, dense):
+    """The full-size workloads with the improved set swept into vertex order
+    every cycle (0) or when a range's set exceeds 1,024 vertices."""
+    with open(os.path.join(GOLDEN, name + ".json")) as fh:
+        rec = json.load(fh)
+    inst = _build(rec)
+    _say("case", name, "dense", dense)
+    res, cnt, lab = gpu_solve(solver, torch, inst, dense=dense)
     assert res.tuple() == (rec["T"], rec["X"], rec["x"], rec["Y"], rec["F2"])
     assert cnt.asdict() == rec["counters"]
     assert hashlib.sha256(lab.astype("<u4").tobytes()).hexdigest() == rec["labels_sha256"]
