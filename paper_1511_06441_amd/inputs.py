@@ -232,6 +232,150 @@ def cube_boundary_to_center(n: int, seed: int, K: int = 100, M: int = 10000) -> 
                     name=f"cube{n}_boundary_s{seed}", meta=dict(seed=seed, K1=K, K2=K))
 
 
+# ----------------------------------------------------------------------------
+# the environments of section 7 (passage times in {1, 2})
+# ----------------------------------------------------------------------------
+
+def _unit_weights_plane(m: int):
+    """A (2m+1) x (2m+1) square standing for [-m, m] x [0, 2m]: vertex
+    (x, y) is index (x + m) + (2m+1) y.  Returns (n, f1) with every edge at 2
+    (padding 0) and a setter for single edges."""
+    n = 2 * m + 1
+    N = n * n
+    f1 = np.full(2 * N, 2, dtype=np.uint8)
+    f1[padding_mask(2, n)] = 0
+    return n, N, f1
+
+
+def _mark_edge(f1, n, N, a, b, value=1):
+    """Set f1 of the lattice edge joining plane points a and b (unit step)."""
+    (xa, ya), (xb, yb) = a, b
+    m = (n - 1) // 2
+    if ya == yb and abs(xa - xb) == 1:
+        x0 = min(xa, xb)
+        if -m <= x0 < m and 0 <= ya < n:
+            f1[0 * N + (x0 + m) + n * ya] = value
+    elif xa == xb and abs(ya - yb) == 1:
+        y0 = min(ya, yb)
+        if -m <= xa <= m and 0 <= y0 < n - 1:
+            f1[1 * N + (xa + m) + n * y0] = value
+    else:
+        raise ValueError("not a unit step")
+
+
+def _staircase(p, q):
+    """Lattice points of a monotone staircase from p to q (integer points)
+    that stays within half a step of the straight segment pq."""
+    (x0, y0), (x1, y1) = p, q
+    dx, dy = x1 - x0, y1 - y0
+    sx, sy = (1 if dx > 0 else -1), (1 if dy > 0 else -1)
+    ax, ay = abs(dx), abs(dy)
+    pts = [(x0, y0)]
+    x, y, i, j = x0, y0, 0, 0
+    while i < ax or j < ay:
+        # step in the direction whose next point lies closer to the segment
+        if j == ay or (i < ax and (2 * i + 1) * ay < (2 * j + 1) * ax):
+            x += sx
+            i += 1
+        else:
+            y += sy
+            j += 1
+        pts.append((x, y))
+    return pts
+
+
+def lemma1_environment(m: int, M: int | None = None) -> Instance:
+    """Section 7, Lemma 1: on [-m, m] x [0, 2m] every edge of the y-axis has
+    passage time 1 and every other edge 2; water starts on the whole x-axis.
+    The lemma takes M infinite: here f2 = f1 and M exceeds every path weight,
+    so a label is M minus the first arrival time.  B is the top of the
+    y-axis, (0, 2m), reached at T = 2m."""
+    n, N, f1 = _unit_weights_plane(m)
+    for y in range(n - 1):
+        _mark_edge(f1, n, N, (0, y), (0, y + 1))
+    f2 = f1.copy()
+    A = np.zeros(N, np.uint8)
+    A[:n] = 1
+    B = np.zeros(N, np.uint8)
+    B[m + n * (n - 1)] = 1
+    M = M if M is not None else 2 * N + 1
+    return Instance(2, n, f1, f2, A, B, M, name=f"lemma1_m{m}", meta=dict(m=m))
+
+
+def fractal_environment(k: int, M: int | None = None, levels: int | None = None) -> Instance:
+    """Section 7, Theorem 2's construction at t = 2^k: the y-axis and the
+    segment LO (L = (-t/2, 0), O = (0, t/2), T = (0, t)) get passage time 1,
+    then k-1 times every triangle (L, O, T) of the current set gets time 1 on
+    L0 X and T0 X (L0, T0 the midpoints of LO and TO, X the midpoint of LT)
+    and is replaced by (L, L0, X) and (X, T0, T); the whole is mirrored in
+    the y-axis.  Segments are laid on the lattice as monotone staircases.
+    Every other edge has time 2; f2 = f1, M above every path weight, water
+    starts on the x-axis and B is T.  The lattice is [-t, t] x [0, 2t].
+    `levels` (1..k, default k) stops the refinement early: omega_levels."""
+    t = 1 << k
+    levels = k if levels is None else levels
+    if not 1 <= levels <= k:
+        raise ValueError("levels must be in 1..k")
+    m = t
+    n, N, f1 = _unit_weights_plane(m)
+    marked = set()
+
+    def seg(p, q):
+        pts = _staircase((round(p[0]), round(p[1])), (round(q[0]), round(q[1])))
+        for a, b in zip(pts[:-1], pts[1:]):
+            for sgn in (1, -1):
+                marked.add(((sgn * a[0], a[1]), (sgn * b[0], b[1])))
+
+    for y in range(t):
+        marked.add(((0, y), (0, y + 1)))
+    L, O, T = (-t / 2, 0.0), (0.0, t / 2), (0.0, float(t))
+    seg(L, O)
+    tris = [(L, O, T)]
+
+    def mid(a, b):
+        return ((a[0] + b[0]) / 2, (a[1] + b[1]) / 2)
+
+    for _ in range(levels - 1):
+        nxt = []
+        for (l, o, tt) in tris:
+            l0, t0, x = mid(l, o), mid(tt, o), mid(l, tt)
+            seg(l0, x)
+            seg(t0, x)
+            nxt += [(l, l0, x), (x, t0, tt)]
+        tris = nxt
+    for a, b in marked:
+        _mark_edge(f1, n, N, a, b)
+    f2 = f1.copy()
+    A = np.zeros(N, np.uint8)
+    A[:n] = 1
+    B = np.zeros(N, np.uint8)
+    B[m + n * t] = 1
+    M = M if M is not None else 2 * N + 1
+    return Instance(2, n, f1, f2, A, B, M, name=f"fractal_k{k}_l{levels}", meta=dict(k=k, t=t, levels=levels))
+
+
+def binary_environment(m: int, p: float, seed: int, M: int | None = None) -> Instance:
+    """Section 7's random environment: on [-m, m] x [0, 2m] every edge has
+    passage time 1 with probability p and 2 otherwise, independently (draw
+    i of stream edge_stream_state(seed, 1) over the SoA index, 1 when its top
+    53 bits as a fraction fall below p).  f2 = f1 and M above every path
+    weight (the section's M = infinity); water starts on the x-axis and B is
+    the top row."""
+    n, N, f1 = _unit_weights_plane(m)
+    z = stream(edge_stream_state(seed, 1), 2 * N)
+    u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    pad = f1 == 0
+    f1 = np.where(u < p, 1, 2).astype(np.uint8)
+    f1[pad] = 0
+    f2 = f1.copy()
+    A = np.zeros(N, np.uint8)
+    A[:n] = 1
+    B = np.zeros(N, np.uint8)
+    B[n * (n - 1):] = 1
+    M = M if M is not None else 2 * N + 1
+    return Instance(2, n, f1, f2, A, B, M, name=f"binary_m{m}_p{p}_s{seed}", meta=dict(m=m, p=p, seed=seed))
+
+
 def _round_half_up(x: float) -> int:
     return int(math.floor(x + 0.5))
 

@@ -33,13 +33,14 @@ def solver(torch):
     s.close()
 
 
-def _gpu_trace(solver, torch, inst, cap, blocks=0, path=0):
+def _gpu_trace(solver, torch, inst, cap, blocks=0, path=0, dense=-1):
     from paper_1511_06441_amd import csp
     di = csp.to_device(inst)
     tr = torch.full((cap, 4), -7, dtype=torch.int64, device="cuda")
     csp.csp_set_trace(solver.ctx, tr)
     csp.csp_set_blocks(solver.ctx, blocks)
     csp.csp_set_path(solver.ctx, path)
+    csp.csp_set_dense_threshold(solver.ctx, dense)
     try:
         res, cnt = solver.solve(di)
         rows = csp.csp_last_trace_rows(solver.ctx)
@@ -47,6 +48,7 @@ def _gpu_trace(solver, torch, inst, cap, blocks=0, path=0):
         csp.csp_set_trace(solver.ctx, None)
         csp.csp_set_blocks(solver.ctx, 0)
         csp.csp_set_path(solver.ctx, 0)
+        csp.csp_set_dense_threshold(solver.ctx, -1)
     torch.cuda.synchronize()
     return res, cnt, rows, tr.cpu().numpy()
 
@@ -118,3 +120,26 @@ def test_trace_at_scale_matches_counters(solver, torch, name):
     transit = sent0 + np.cumsum(tr[:, 3] - tr[:, 1])
     assert (transit >= 0).all()
     assert max(sent0, int(transit.max())) == c["P"]
+
+
+# the environments of section 7 (passage times 1 and 2, M above every path
+# weight): Lemma 1's, Theorem 2's construction and Theorem 1's random one
+SECTION7 = [lambda: gen.lemma1_environment(100), lambda: gen.fractal_environment(8),
+            lambda: gen.fractal_environment(7, levels=3), lambda: gen.binary_environment(150, 0.3, 5),
+            lambda: gen.binary_environment(150, 0.7, 6)]
+
+
+@pytest.mark.parametrize("k", range(len(SECTION7)))
+@pytest.mark.parametrize("dense", [0, 0xFFFFFFFF])
+@pytest.mark.parametrize("blocks", [0, 16])
+def test_section7_environments_trace(solver, torch, k, dense, blocks):
+    """Active set and deliveries per cycle on the adversarial environments,
+    row by row against the oracle, in both forms of the improved set."""
+    from oracle import oracle as O
+    inst = SECTION7[k]()
+    _say("case", inst.name, "dense", dense, "blocks", blocks)
+    ref = O.solve_instance(inst, trace_cap=1 << 16)
+    res, cnt, rows, tr = _gpu_trace(solver, torch, inst, 1 << 16, blocks=blocks, dense=dense)
+    assert res.tuple() == ref.tuple() and cnt.asdict() == ref.counters
+    assert rows == len(ref.trace)
+    assert np.array_equal(tr[:rows], ref.trace), inst.name
