@@ -3,9 +3,10 @@
 
 One step = the whole hot path (input checks, the persistent cycle kernel,
 result read-back) for every solve of one workload, with inputs already
-resident in HBM.  Default workload: the 128^3 cube (d=3, f1, f2 i.i.d.
-uniform on 1..10 from seed 11, A = face x=0, B = face x=127) solved for
-M = 400, 700 and 1000, i.e. three solves per step.
+resident in HBM.  Default workload: the 256^3 cube (d=3, f1, f2 i.i.d.
+uniform on 1..100 from seed 21, A = face x=0, B = face x=255, M = 10000),
+one solve per step.  The 128^3 cube (three solves, M = 400, 700, 1000) and
+the other workloads are options.
 
 Prints ONE JSON line.  ``value`` is active-edge relaxations per second
 (flows delivered, summed over the step's solves, divided by wall time);
@@ -26,26 +27,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-LABEL_BYTES = 4                # label words are uint32
 FLOW_BYTES = 8                 # (destination, quality|direction)
 
 WORKLOADS = {
     "cube128": dict(desc="d=3 n=128 (2,097,152 vertices, 6,242,304 edges), f1,f2 iid U{1..10} "
                          "splitmix64 seed 11, A=face x=0, B=face x=127, M in {400,700,1000}",
                     build=lambda gen: [gen.cube128(11, M) for M in (400, 700, 1000)],
-                    sample_index=2),
+                    sample_index=2, label_bytes=2),
     "cube256": dict(desc="d=3 n=256 (16,777,216 vertices, 50,135,040 edges), f1,f2 iid U{1..100} "
                          "seed 21, A=face x=0, B=face x=255, M=10000",
-                    build=lambda gen: [gen.cube256(21)], sample_index=None),
+                    build=lambda gen: [gen.cube256(21)], sample_index=0, sample_cycles=(300, 900),
+                    label_bytes=4),
     "cube256stress": dict(desc="d=3 n=256, f1=1, f2 iid U{1..3} seed 22, faces x=0 -> x=255, M=10000",
-                          build=lambda gen: [gen.cube256_stress(22)], sample_index=None),
+                          build=lambda gen: [gen.cube256_stress(22)], sample_index=0, sample_cycles=(60, 180),
+                          label_bytes=4),
     "square64": dict(desc="d=2 n=64, f1,f2 iid U{1..5} seed 1, columns x=0 -> x=63, M=200",
-                     build=lambda gen: [gen.square64(1)], sample_index=0),
+                     build=lambda gen: [gen.square64(1)], sample_index=0, label_bytes=2),
     "paper_cubes": dict(desc="the paper's runs (section 8): d=3 cubes n=50,75,100,125, water on the cube "
                              "boundary, B the centre vertex, f1,f2 iid U{1..100} seed 61, M=10000",
                         build=lambda gen: [gen.cube_boundary_to_center(n, 61, K=100, M=10000)
                                            for n in (50, 75, 100, 125)],
-                        sample_index=3),
+                        sample_index=3, label_bytes=4),
 }
 
 BATCH_DESC = ("1,024 independent problems (master seed 41): d in {2,3}, side log-uniform in [32,512] (d=2) / "
@@ -311,11 +313,11 @@ def run_recon(args):
     solver.close()
 
 
-def algorithmic_bytes(N, c):
-    """Bytes the method must move for one solve (label init, own label per
-    improvement, f1+f2+neighbour label per test, one flow record written per
-    send, one flow record read plus a label read-modify-write per delivery)."""
-    L = LABEL_BYTES
+def algorithmic_bytes(N, c, L=4):
+    """Bytes the method must move for one solve with L-byte labels (label
+    init, own label per improvement, f1+f2+neighbour label per test, one flow
+    record written per send, one flow record read plus a label
+    read-modify-write per delivery)."""
     return (N * L + c["U"] * L + c["D"] * (2 + L) + c["E"] * FLOW_BYTES
             + c["R"] * (FLOW_BYTES + 2 * L))
 
@@ -359,15 +361,64 @@ def measured_traffic(workload):
     return float(m_b.group(1))
 
 
-def cpu_baseline(inst):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_run(inst, max_cycles):
     from oracle import oracle as O
     t0 = time.perf_counter()
-    r = O.solve_instance(inst, want_labels=False)
-    dt = time.perf_counter() - t0
-    return dict(value=r.counters["R"] / dt, unit="relaxations/s", cores=1, kind="oracle",
-                sample=f"one solve of {inst.name} (single-threaded C oracle, -O2), "
-                       f"{dt:.1f} s, R={r.counters['R']}",
-                seconds=round(dt, 2))
+    r = O.solve_instance(inst, want_labels=False, max_cycles=max_cycles)
+    return r.counters["R"], time.perf_counter() - t0
+
+
+def _oracle_window(args):
+    """Relaxations/s of the oracle over cycles k1+1..k2 of one instance (two
+    prefix runs; the difference removes set-up and the small first cycles)."""
+    wl, k1, k2 = args
+    inst = WORKLOADS[wl]["build"](_gen())[WORKLOADS[wl]["sample_index"]]
+    R1, t1 = _oracle_run(inst, k1)
+    R2, t2 = _oracle_run(inst, k2)
+    return (R2 - R1) / (t2 - t1), R2 - R1, t2 - t1
+
+
+def _gen():
+    from paper_1511_06441_amd import inputs as gen
+    return gen
+
+
+def cpu_baseline(workload, inst):
+    """The oracle timed on this host: one thread, and the same sample run in
+    as many concurrent processes as the host gives this job (at most 16)."""
+    import multiprocessing as mp
+    wl = WORKLOADS[workload]
+    nproc = len(os.sched_getaffinity(0))
+    procs = max(1, min(16, nproc))
+    if "sample_cycles" in wl:
+        k1, k2 = wl["sample_cycles"]
+        v, R, dt = _oracle_window((workload, k1, k2))
+        with mp.get_context("fork").Pool(procs) as pool:
+            par = pool.map(_oracle_window, [(workload, k1, k2)] * procs)
+        sample = (f"cycles {k1 + 1}..{k2} of {inst.name} (difference of two prefix runs of the single-threaded "
+                  f"C oracle, -O2): R={R} in {dt:.1f} s")
+        par_v = sum(x[0] for x in par)
+    else:
+        R, dt = _oracle_run(inst, 0)
+        v = R / dt
+        with mp.get_context("fork").Pool(procs) as pool:
+            par = pool.starmap(_oracle_run, [(inst, 0)] * procs)
+        sample = f"one whole solve of {inst.name} (single-threaded C oracle, -O2), {dt:.1f} s, R={R}"
+        par_v = sum(r / t for r, t in par)
+    return dict(value=v, unit="relaxations/s", cores=1, kind="oracle", sample=sample, seconds=round(dt, 2),
+                cpu_model=_cpu_model(), nproc=nproc,
+                parallel={"value": par_v, "processes": procs,
+                          "how": "the same sample in concurrent processes, one instance each; sum of their rates"})
 
 
 def main():
@@ -375,7 +426,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["batch1024", "serve", "recon", "graph128"])
+    ap.add_argument("--workload", default="cube256", choices=sorted(WORKLOADS) + ["batch1024", "serve", "recon", "graph128"])
     ap.add_argument("--batch-count", type=int, default=1024)
     ap.add_argument("--plain", action="store_true", help="batch workload: also time sequential plain launches")
     ap.add_argument("--serve-count", type=int, default=8)
@@ -444,7 +495,7 @@ def main():
 
     R_step = sum(c.R for _, c, _ in runs[0])
     solves = len(dev) * args.steps
-    bytes_step = sum(algorithmic_bytes(i.N, c.asdict()) for i, (_, c, _) in zip(insts, runs[0]))
+    bytes_step = sum(algorithmic_bytes(i.N, c.asdict(), wl["label_bytes"]) for i, (_, c, _) in zip(insts, runs[0]))
     kern_ms = [ms for st in runs for (_, _, ms) in st]
     kern_ms_step = sum(kern_ms) / args.steps
     achieved = bytes_step / (kern_ms_step * 1e-3) / 1e9
@@ -459,7 +510,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u16" if wl["label_bytes"] == 2 else "u32",
         "data": "synthetic (seeded splitmix64 lattices)",
         "config": {"workload": args.workload, "desc": wl["desc"], "solves_per_step": len(dev),
                    "parallelism": "single GPU"},
@@ -486,7 +537,7 @@ def main():
     if args.trace:
         line["trace"] = [trace_summary(csp, solver, torch, di) for di in dev]
     if not args.no_cpu_baseline and wl["sample_index"] is not None:
-        line["cpu_baseline"] = cpu_baseline(insts[wl["sample_index"]])
+        line["cpu_baseline"] = cpu_baseline(args.workload, insts[wl["sample_index"]])
     print(json.dumps(line), flush=True)
     solver.close()
 

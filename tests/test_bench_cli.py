@@ -40,9 +40,26 @@ def test_traffic_read_only_for_the_current_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("square64") is None           # no summary at all
 
 
-@pytest.mark.parametrize("N,c,expect", [
-    (10, dict(U=0, D=0, E=0, R=0), 40),
-    (1, dict(U=1, D=1, E=1, R=1), 4 + 4 + 6 + 8 + 16),
+@pytest.mark.parametrize("N,c,L,expect", [
+    (10, dict(U=0, D=0, E=0, R=0), 4, 40),
+    (1, dict(U=1, D=1, E=1, R=1), 4, 4 + 4 + 6 + 8 + 16),
+    (1, dict(U=1, D=1, E=1, R=1), 2, 2 + 2 + 4 + 8 + 12),
 ])
-def test_algorithmic_bytes(N, c, expect):
-    assert bench.algorithmic_bytes(N, c) == expect
+def test_algorithmic_bytes(N, c, L, expect):
+    assert bench.algorithmic_bytes(N, c, L) == expect
+
+
+def test_label_width_follows_the_workload():
+    """Configurations with 16-bit labels count 2-byte label traffic; the
+    256^3 cubes count 4 bytes."""
+    assert bench.WORKLOADS["square64"]["label_bytes"] == 2
+    assert bench.WORKLOADS["cube128"]["label_bytes"] == 2
+    assert bench.WORKLOADS["cube256"]["label_bytes"] == 4
+    assert bench.WORKLOADS["cube256stress"]["label_bytes"] == 4
+
+
+def test_cpu_window_sample_is_bounded():
+    """The 256^3 CPU sample is a window of cycles (two prefix runs), not a
+    whole solve."""
+    k1, k2 = bench.WORKLOADS["cube256"]["sample_cycles"]
+    assert 0 < k1 < k2 <= 2000
