@@ -5,7 +5,13 @@ here touches the HIP library.  Each case is stored as JSON with T, X, x, Y,
 F2, the counters and the SHA-256 of the final labels (uint32, little
 endian).
 
-    python tests/golden/make_golden.py [name ...]
+Two cases hold many problems and run the oracle in parallel host
+processes: ``batch1024`` (the 1,024 problems of the mixed batch, master seed
+41) and ``serve8`` (the first 8 serving requests of master seed 51, each with
+its path recovered by repeated solves, section 1 and section 5
+"Termination").
+
+    python tests/golden/make_golden.py [name ...] [--workers K]
 """
 from __future__ import annotations
 
@@ -55,8 +61,73 @@ def make(name, builder):
     print(name, r.tuple(), r.counters, f"{dt:.1f}s", flush=True)
 
 
+def _batch_one(j):
+    inst = gen.mixed_instance(41, j)
+    t0 = time.time()
+    r = O.solve_instance(inst)
+    dt = time.time() - t0
+    return dict(j=j, d=inst.d, n=inst.n, K=inst.meta["K"], M=inst.M, seed=inst.meta["seed"],
+                T=r.T, X=r.X, x=r.x, Y=r.Y, F2=r.F2, counters=r.counters,
+                labels_sha256=labels_sha256(r.labels), oracle_seconds=round(dt, 2))
+
+
+def _serve_one(k):
+    inst = gen.mixed_instance(51, k, (64, 1024), (32, 256))
+    t0 = time.time()
+    r = O.solve_instance(inst)
+    path, rp, steps = O.reconstruct(inst.d, inst.n, inst.f1, inst.f2, inst.A, inst.B, inst.M)
+    dt = time.time() - t0
+    assert rp.tuple() == r.tuple()
+    return dict(k=k, d=inst.d, n=inst.n, K=inst.meta["K"], M=inst.M, seed=inst.meta["seed"],
+                T=r.T, X=r.X, x=r.x, Y=r.Y, F2=r.F2, counters=r.counters,
+                labels_sha256=labels_sha256(r.labels), path=[int(v) for v in path],
+                resolves=[[int(v) for v in row] for row in steps], oracle_seconds=round(dt, 2))
+
+
+def make_many(name, fn, items, workers, desc):
+    """Run fn over items in `workers` host processes, largest first, and store
+    the records in input order."""
+    import multiprocessing as mp
+    t0 = time.time()
+    out = {}
+    with mp.get_context("fork").Pool(workers) as pool:
+        for rec in pool.imap_unordered(fn, items):
+            key = rec.get("j", rec.get("k"))
+            out[key] = rec
+            print(f"{name}: {len(out)}/{len(items)} (item {key}, {rec['oracle_seconds']} s, "
+                  f"{time.time() - t0:.0f} s elapsed)", flush=True)
+    recs = [out[k] for k in sorted(out)]
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(dict(name=name, desc=desc, problems=recs,
+                       oracle_seconds=round(sum(r["oracle_seconds"] for r in recs), 2)), fh, indent=0)
+
+
+def batch1024(workers):
+    ps = gen.batch_params(1024, 41)
+    order = sorted(range(1024), key=lambda j: -(ps[j][2] ** ps[j][1]) * ps[j][4])
+    make_many("batch1024_s41", _batch_one, order, workers,
+              "the 1,024 problems of the mixed batch (master seed 41), oracle solves with labels")
+
+
+def serve8(workers):
+    ps = gen.serving_params(8, 51)
+    order = sorted(range(8), key=lambda k: -(ps[k][2] ** ps[k][1]) * ps[k][4])
+    make_many("serve8_s51", _serve_one, order, workers,
+              "the first 8 serving requests (master seed 51): solve and path by repeated solves")
+
+
 if __name__ == "__main__":
+    args = [a for a in sys.argv[1:] if not a.startswith("--workers")]
+    workers = 7
+    for a in sys.argv[1:]:
+        if a.startswith("--workers="):
+            workers = int(a.split("=", 1)[1])
     all_cases = cases()
-    names = sys.argv[1:] or list(all_cases)
+    names = args or list(all_cases)
     for nm in names:
-        make(nm, all_cases[nm])
+        if nm == "batch1024":
+            batch1024(workers)
+        elif nm == "serve8":
+            serve8(workers)
+        else:
+            make(nm, all_cases[nm])

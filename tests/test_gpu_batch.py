@@ -178,3 +178,43 @@ def test_candidate_phase_overflow_always_retried(solver, torch):
             assert cnt[0].asdict() == ref.counters, (k, cnt[0].asdict(), ref.counters)
     finally:
         csp.csp_set_batch_target(solver.ctx, 0)
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name + ".json")) as fh:
+        return json.load(fh)
+
+
+def test_config4_full_batch_vs_stored_oracle(solver, torch):
+    """All 1,024 problems of the mixed batch (master seed 41, 306,237,961
+    vertices) in one csp_solve_batch call against the oracle's stored
+    outputs: T, X, x, Y, F2, every counter and the SHA-256 of every
+    problem's labels.  The edges are drawn on the GPU with the same seeded
+    generator (checked against the host draw by the CPU tests)."""
+    import hashlib
+    from paper_1511_06441_amd import csp
+    rec = _golden("batch1024_s41")["problems"]
+    assert len(rec) == 1024
+    dev, labs = [], []
+    for j, g in enumerate(rec):
+        s, d, n, K, M = gen.mixed_params(41, j)
+        assert (d, n, K, M, s) == (g["d"], g["n"], g["K"], g["M"], g["seed"])
+        f1, f2 = gen.lattice_edges_torch(d, n, s, K, K, device="cuda")
+        dev.append(csp.DeviceInstance(d, n, f1, f2, gen.face_mask_torch(d, n, 0, 0, "cuda"),
+                                      gen.face_mask_torch(d, n, 0, n - 1, "cuda"), M))
+        labs.append(torch.zeros(n ** d, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    _say("config-4 batch of 1,024 problems")
+    res, cnt = csp.csp_solve_batch(solver.ctx, dev, labels=labs)
+    torch.cuda.synchronize()
+    _say("  batch kernel ms %.3f" % csp.csp_last_kernel_ms(solver.ctx))
+    bad = []
+    for j, g in enumerate(rec):
+        lab = labs[j].cpu().numpy().view(np.uint32)
+        ok = (res[j].tuple() == (g["T"], g["X"], g["x"], g["Y"], g["F2"]) and cnt[j].asdict() == g["counters"]
+              and hashlib.sha256(lab.astype("<u4").tobytes()).hexdigest() == g["labels_sha256"])
+        if not ok:
+            bad.append(j)
+    assert not bad, ("problems differing from the oracle", bad[:20])

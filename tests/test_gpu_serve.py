@@ -193,3 +193,103 @@ def test_serve_idle_then_again(server, torch):
         while time.perf_counter() - t0 < 0.05:
             server.poll()
             time.sleep(0.005)
+
+
+def _submit_watching(srv, devs, recon):
+    """Submit every request without polling in between; the largest number
+    seen waiting for admission."""
+    most = 0
+    for k, di in enumerate(devs):
+        srv.submit(di, reconstruct=recon, tag=k)
+        most = max(most, srv.pending()[0])
+    return most
+
+
+def _collect(srv, count):
+    done = {}
+    for c in srv.drain():
+        done[c.tag] = c
+    assert sorted(done) == list(range(count))
+    return done
+
+
+@pytest.mark.parametrize("limit", ["job_slots", "arena", "workers"])
+def test_serve_requests_wait_for_admission(solver, torch, limit):
+    """Requests that cannot all be on the GPU at once wait until a job slot
+    (max_jobs = 1), arena memory (12 MiB for 2-4 MB requests) or workers (gangs
+    of 16 workgroups, 24 requests against one workgroup per CU) free up; every
+    result, path included, equals the oracle's."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    if limit == "workers":
+        # M above 65,535 keeps 32-bit labels in LDS: ranges of 32K vertices,
+        # so an 80^3 request takes a gang of 16 workgroups
+        base = [gen.opposite_faces(3, 80, 71, 10, 10, 70000), gen.opposite_faces(3, 80, 72, 10, 10, 70001)]
+        insts = [base[k % 2] for k in range(24)]
+        srv = csp.Server(solver, arena_bytes=16 << 30, max_jobs=64)
+        recon = False
+    else:
+        base = [gen.opposite_faces(2, 120, 73, 6, 6, 500), gen.opposite_faces(2, 100, 74, 6, 6, 400),
+                gen.opposite_faces(3, 30, 75, 8, 8, 300)]
+        insts = [base[k % 3] for k in range(9)]
+        srv = csp.Server(solver, arena_bytes=(1 << 30) if limit == "job_slots" else (12 << 20),
+                         max_jobs=1 if limit == "job_slots" else 64)
+        recon = True
+    try:
+        devs = [csp.to_device(i) for i in insts]
+        torch.cuda.synchronize()
+        _say("serving", len(devs), "requests, limited by", limit)
+        most = _submit_watching(srv, devs, recon)
+        done = _collect(srv, len(devs))
+    finally:
+        srv.close()
+    assert most >= 1, "no request had to wait"
+    refs = {}
+    for k, inst in enumerate(insts):
+        key = id(inst)
+        if key not in refs:
+            if recon:
+                refs[key] = _oracle_request(inst)
+            else:
+                refs[key] = (O.solve_instance(inst, want_labels=False), [])
+        ref, path = refs[key]
+        c = done[k]
+        assert c.status == 0, (k, c.status)
+        assert c.res == ref.tuple() and c.counters == ref.counters, (k, inst.name)
+        assert c.path == path, (k, inst.name)
+
+
+def test_config5_requests_vs_stored_oracle(solver, torch):
+    """The first 8 serving requests of master seed 51 (2-D sides 64..1024,
+    3-D sides 32..256, up to 1,032,256 vertices), submitted at once to one
+    server: result, counters of the first solve and the whole path recovered
+    by repeated solves equal the oracle's stored outputs."""
+    import json
+    import os
+    from paper_1511_06441_amd import csp
+    with open(os.path.join(os.path.dirname(__file__), "golden", "serve8_s51.json")) as fh:
+        rec = json.load(fh)["problems"]
+    assert len(rec) == 8
+    devs = []
+    for k, g in enumerate(rec):
+        s, d, n, K, M = gen.serving_params(8, 51)[k]
+        assert (d, n, K, M, s) == (g["d"], g["n"], g["K"], g["M"], g["seed"])
+        f1, f2 = gen.lattice_edges_torch(d, n, s, K, K, device="cuda")
+        devs.append(csp.DeviceInstance(d, n, f1, f2, gen.face_mask_torch(d, n, 0, 0, "cuda"),
+                                       gen.face_mask_torch(d, n, 0, n - 1, "cuda"), M))
+    torch.cuda.synchronize()
+    srv = csp.Server(solver, arena_bytes=16 << 30, max_jobs=64)
+    try:
+        _say("config-5: 8 requests with paths")
+        t0 = time.perf_counter()
+        done = _run_all(srv, devs, stagger=0)
+        _say("  served in %.1f s" % (time.perf_counter() - t0))
+    finally:
+        srv.close()
+    for k, g in enumerate(rec):
+        c = done[k]
+        assert c.status == 0, (k, c.status)
+        assert c.res == (g["T"], g["X"], g["x"], g["Y"], g["F2"]), k
+        assert c.counters == g["counters"], k
+        assert c.path == g["path"], k
+        assert c.solves == max(len(g["path"]) - 1, 1)
