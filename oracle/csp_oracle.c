@@ -377,13 +377,21 @@ int orc_solve_lattice(int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
  * path receives the vertices from the A end to X; *len is their number.
  * Returns ORC_EINVAL with *len set to the needed size if cap is too small.
  * steps (may be NULL) receives one {T, X, x, Y, F2} row per solve.
+ *
+ * max_steps > 0 stops the chain after that many rows (the first solve is
+ * row 0): path then holds only the vertices found so far, ending at X, and
+ * *complete is 0.  The chain's steps do not depend on where it stops, so a
+ * stopped chain is a prefix of the whole one (used where the whole chain
+ * would take hours on the host).
  */
-int orc_reconstruct_graph(int64_t nv, const int64_t *off, const int32_t *nbr,
-                          const uint8_t *a1, const uint8_t *a2, const int64_t *eid,
-                          const uint8_t *A, const uint8_t *B, int64_t M,
-                          int64_t *path, int64_t cap, int64_t *len, int64_t *res,
-                          int64_t *steps, int64_t steps_cap)
+static int reconstruct_graph_upto(int64_t nv, const int64_t *off, const int32_t *nbr,
+                                  const uint8_t *a1, const uint8_t *a2, const int64_t *eid,
+                                  const uint8_t *A, const uint8_t *B, int64_t M,
+                                  int64_t *path, int64_t cap, int64_t *len, int64_t *res,
+                                  int64_t *steps, int64_t steps_cap, int64_t max_steps,
+                                  int64_t *complete)
 {
+    *complete = 1;
     int rc = orc_solve_graph(nv, off, nbr, a1, a2, eid, A, B, M, NULL, res,
                              NULL, NULL, 0, NULL, 0);
     if (rc) return rc;
@@ -404,6 +412,7 @@ int orc_reconstruct_graph(int64_t nv, const int64_t *off, const int32_t *nbr,
         int64_t Xv = cur[1], Yv = cur[3], x = cur[2];
         rev[n_rev++] = Yv;
         if (A[Yv]) break;
+        if (max_steps > 0 && nsteps >= max_steps) { *complete = 0; break; }
         /* f1, f2 of the last edge: the entry of X's list with edge id x */
         int64_t w2 = -1;
         for (int64_t j = off[Xv]; j < off[Xv + 1]; ++j)
@@ -428,16 +437,38 @@ int orc_reconstruct_graph(int64_t nv, const int64_t *off, const int32_t *nbr,
     return rc;
 }
 
+int orc_reconstruct_graph(int64_t nv, const int64_t *off, const int32_t *nbr,
+                          const uint8_t *a1, const uint8_t *a2, const int64_t *eid,
+                          const uint8_t *A, const uint8_t *B, int64_t M,
+                          int64_t *path, int64_t cap, int64_t *len, int64_t *res,
+                          int64_t *steps, int64_t steps_cap)
+{
+    int64_t complete;
+    return reconstruct_graph_upto(nv, off, nbr, a1, a2, eid, A, B, M, path, cap, len, res,
+                                  steps, steps_cap, 0, &complete);
+}
+
+int orc_reconstruct_lattice_upto(int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
+                                 const uint8_t *A, const uint8_t *B, int64_t M,
+                                 int64_t *path, int64_t cap, int64_t *len, int64_t *res,
+                                 int64_t *steps, int64_t steps_cap, int64_t max_steps,
+                                 int64_t *complete)
+{
+    orc_adj g;
+    int rc = orc_adj_build(d, n, f1, f2, &g);
+    if (rc) return rc;
+    rc = reconstruct_graph_upto(g.nv, g.off, g.nbr, g.a1, g.a2, g.eid, A, B, M,
+                                path, cap, len, res, steps, steps_cap, max_steps, complete);
+    orc_adj_free(&g);
+    return rc;
+}
+
 int orc_reconstruct_lattice(int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
                             const uint8_t *A, const uint8_t *B, int64_t M,
                             int64_t *path, int64_t cap, int64_t *len, int64_t *res,
                             int64_t *steps, int64_t steps_cap)
 {
-    orc_adj g;
-    int rc = orc_adj_build(d, n, f1, f2, &g);
-    if (rc) return rc;
-    rc = orc_reconstruct_graph(g.nv, g.off, g.nbr, g.a1, g.a2, g.eid, A, B, M,
-                               path, cap, len, res, steps, steps_cap);
-    orc_adj_free(&g);
-    return rc;
+    int64_t complete;
+    return orc_reconstruct_lattice_upto(d, n, f1, f2, A, B, M, path, cap, len, res,
+                                        steps, steps_cap, 0, &complete);
 }

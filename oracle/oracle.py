@@ -55,6 +55,9 @@ def lib():
         L.orc_lattice_adjacency.restype = ctypes.c_int
         L.orc_reconstruct_lattice.argtypes = [ctypes.c_int, i64, p, p, p, p, i64, p, i64, p, p, p, i64]
         L.orc_reconstruct_lattice.restype = ctypes.c_int
+        L.orc_reconstruct_lattice_upto.argtypes = [ctypes.c_int, i64, p, p, p, p, i64, p, i64, p, p,
+                                                   p, i64, i64, p]
+        L.orc_reconstruct_lattice_upto.restype = ctypes.c_int
         L.orc_reconstruct_graph.argtypes = [i64, p, p, p, p, p, p, p, i64, p, i64, p, p, p, i64]
         L.orc_reconstruct_graph.restype = ctypes.c_int
         _lib = L
@@ -191,6 +194,31 @@ def reconstruct(d, n, f1, f2, A, B, M, cap=None):
         raise OracleError(f"oracle reconstruct failed: {rc}")
     L = int(ln[0])
     return path[:L].copy(), Result(*[int(v) for v in res]), steps[:max(L - 1, 0)].copy()
+
+
+def reconstruct_upto(d, n, f1, f2, A, B, M, max_steps):
+    """The first max_steps solves of the repeated-solve chain.
+
+    Returns (vertices, result, rows, complete): the vertices found so far in
+    path order (ending at X; the whole path from the A end when complete),
+    the first solve's result and one {T, X, x, Y, F2} row per solve.
+    """
+    f1, f2, A, B = _u8(f1), _u8(f2), _u8(A), _u8(B)
+    cap = int(max_steps) + 2
+    path = np.zeros(cap, dtype=np.int64)
+    steps = np.zeros((cap, 5), dtype=np.int64)
+    ln = np.zeros(1, dtype=np.int64)
+    res = np.zeros(5, dtype=np.int64)
+    complete = np.zeros(1, dtype=np.int64)
+    rc = lib().orc_reconstruct_lattice_upto(d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), int(M),
+                                            _ptr(path), cap, _ptr(ln), _ptr(res), _ptr(steps),
+                                            cap, int(max_steps), _ptr(complete))
+    if rc != 0:
+        raise OracleError(f"oracle reconstruct failed: {rc}")
+    L = int(ln[0])
+    done = bool(complete[0])
+    nrows = max(L - 1, 0)
+    return path[:L].copy(), Result(*[int(v) for v in res]), steps[:nrows].copy(), done
 
 
 def reconstruct_graph(graph, A, B, M, cap=None):

@@ -791,6 +791,27 @@ __device__ __forceinline__ void comb_wave(unsigned &mn, unsigned &orf, unsigned 
     }
 }
 
+// Wait until every memory access the calling wave has issued is complete.
+// The compiler may not move memory accesses across it.
+__device__ __forceinline__ void vm_drain()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ void release_(bool lite)
+{
+    if (lite) vm_drain();
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+__device__ __forceinline__ void acquire_(bool lite)
+{
+    if (lite) __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // Tree barrier among the g workgroups of a gang (member m is the caller)
 // that combines one Comb per member.  Members write their Comb to a private
 // slot line, publish with an agent-scope release fence and count themselves
@@ -800,11 +821,21 @@ __device__ __forceinline__ void comb_wave(unsigned &mn, unsigned &orf, unsigned 
 // epoch, into every member's flag line.  Waiters spin on their own line; a
 // wait that outlasts `limit` wall-clock ticks marks the gang broken and the
 // call returns false, so a logic error drains the gang instead of hanging.
+//
+// lite: everything the members exchange around this barrier is stored and
+// loaded with agent-scope atomics (the barrier's own words, and the caller's
+// candidates and their fills), which are coherent across the XCDs' L2 caches
+// by themselves.  The barrier then only waits for each wave's accesses to
+// complete before publishing, instead of writing back and invalidating the
+// L2 (which would also evict the edge records and wheel lines each
+// workgroup keeps reusing).
 __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
-                             const Comb &mine, Comb &out, bool need_rest, unsigned long long *tpub = nullptr)
+                             const Comb &mine, Comb &out, bool need_rest, unsigned long long *tpub = nullptr,
+                             bool lite = false)
 {
     __shared__ int s_ok;
     __shared__ unsigned long long s_o[5];
+    if (lite) vm_drain();
     __syncthreads();
     ++epoch;
     if (g == 1) {
@@ -825,7 +856,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
             st64(&sl[2], mine.s1);
             st64(&sl[3], mine.s2);
             st64(&sl[4], mine.mx);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            release_(lite);
             const unsigned a = __hip_atomic_fetch_add(&bh->grp[grp][0], 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             leader = a == members - 1;
@@ -833,7 +864,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
         }
         leader = __shfl(leader, 0);
         if (leader) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            acquire_(lite);
             unsigned mn = 0xFFFFFFFFu, orf = 0;
             unsigned long long s0 = 0, s1 = 0, s2 = 0, mx = 0;
             for (unsigned j = lane; j < members; j += 64) {
@@ -856,7 +887,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
                 st64(&gs[2], s1);
                 st64(&gs[3], s2);
                 st64(&gs[4], mx);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                release_(lite);
                 const unsigned rr = __hip_atomic_fetch_add(&bh->root[0], 1u, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);
                 releaser = rr == ngrp - 1;
@@ -864,7 +895,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
             }
             releaser = __shfl(releaser, 0);
             if (releaser) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                acquire_(lite);
                 mn = 0xFFFFFFFFu;
                 orf = 0;
                 s0 = s1 = s2 = mx = 0;
@@ -888,7 +919,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
                     st64(&rs[2], s2);
                     st64(&rs[3], mx);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                release_(lite);
                 const unsigned long long w = ((unsigned long long)epoch << 32) |
                                              ((unsigned long long)(orf >> 28) << 16) | (mn < 0xFFFFu ? mn : 0xFFFFu);
                 for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], w);
@@ -908,7 +939,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
                     break;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            acquire_(lite);
             if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
             const unsigned mn16 = (unsigned)(w & 0xFFFFu), orf = (unsigned)((w >> 16) & 0xFu) << 28;
             s_o[0] = (unsigned long long)(mn16 == 0xFFFFu ? 0xFFFFFFFFu : mn16) | ((unsigned long long)orf << 32);
@@ -1028,6 +1059,21 @@ __device__ __forceinline__ bool lraise(unsigned *lw, bool l16, unsigned i, unsig
 }
 
 constexpr unsigned CAND_LI = 0x1FFFFu;     // candidate word 0: local index | f1 << 17 | dir << 25
+
+// Candidates cross workgroups inside the cycle loop, whose barrier writes
+// back no cache: they are stored and loaded with agent-scope atomics.
+__device__ __forceinline__ void cand_put(uint2 *p, unsigned w0, unsigned w1)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)w0 | ((unsigned long long)w1 << 32),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint2 cand_get(const uint2 *p)
+{
+    const unsigned long long v =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_uint2((unsigned)v, (unsigned)(v >> 32));
+}
 constexpr unsigned SF_BAD = 1u << 28;      // an edge with f1 or f2 equal to 0
 
 // Range r of job p, run by the calling workgroup.  smem is the dynamic LDS
@@ -1503,8 +1549,10 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                     first = __shfl(first, leader);
                     const unsigned pos = first + (unsigned)__popcll(grp & ((1ull << lane) - 1ull));
                     if (pos < CS) {
-                        candbuf(par, r, oi)[pos] = make_uint2(li | (a1 << 17) | (rdir << 25), (unsigned)q);
-                        if constexpr (LOG) p.cptr[(candbuf(par, r, oi) - cand) + pos] = myrec;
+                        cand_put(candbuf(par, r, oi) + pos, li | (a1 << 17) | (rdir << 25), (unsigned)q);
+                        if constexpr (LOG)
+                            __hip_atomic_store(&p.cptr[(candbuf(par, r, oi) - cand) + pos], myrec, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     } else {
                         atomicOr(&s_flags, SF_OVER);
                     }
@@ -1549,7 +1597,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         mine.s1 = nlist;
         mine.s2 = transit;
         mine.mx = s_xkey;
-        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false, p.prof ? &s_tpub : nullptr)) {
+        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false, p.prof ? &s_tpub : nullptr, true)) {
             status = ST_BROKEN;
             break;
         }
@@ -1675,8 +1723,10 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                     while (j >= s_cpre[oi + 1]) ++oi;
                     const long long src = (long long)r - soff(oi);
                     const uint2 *cb = candbuf(par, (unsigned long long)src, (unsigned)oi);
-                    cdu[u] = cb[j - s_cpre[oi]];
-                    if constexpr (LOG) cpu[u] = p.cptr[(cb - cand) + (j - s_cpre[oi])];
+                    cdu[u] = cand_get(cb + (j - s_cpre[oi]));
+                    if constexpr (LOG)
+                        cpu[u] = __hip_atomic_load(&p.cptr[(cb - cand) + (j - s_cpre[oi])], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
                 }
               }
 #pragma unroll

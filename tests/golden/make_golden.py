@@ -9,9 +9,11 @@ Two cases hold many problems and run the oracle in parallel host
 processes: ``batch1024`` (the 1,024 problems of the mixed batch, master seed
 41) and ``serve8`` (the first 8 serving requests of master seed 51, each with
 its path recovered by repeated solves, section 1 and section 5
-"Termination").
+"Termination"); where a request's whole chain would take hours on the host
+only its first solves are stored, and ``serve8_pathK`` stores request K's
+whole chain on its own.
 
-    python tests/golden/make_golden.py [name ...] [--workers K]
+    python tests/golden/make_golden.py [name ...] [--workers=K]
 """
 from __future__ import annotations
 
@@ -71,17 +73,41 @@ def _batch_one(j):
                 labels_sha256=labels_sha256(r.labels), oracle_seconds=round(dt, 2))
 
 
-def _serve_one(k):
+# Above this many vertices the whole repeated-solve chain would keep one host
+# core busy for hours (the 1016^2 request: about 68 s per solve and some
+# 1,500 solves), so only its first SERVE_PREFIX_STEPS solves are stored; the
+# stored rows are a prefix of the whole chain (the chain does not depend on
+# where it stops).
+SERVE_FULL_PATH_MAX_VERTICES = 300_000
+SERVE_PREFIX_STEPS = 24
+
+
+def _serve_one(k, full=False):
     inst = gen.mixed_instance(51, k, (64, 1024), (32, 256))
     t0 = time.time()
     r = O.solve_instance(inst)
-    path, rp, steps = O.reconstruct(inst.d, inst.n, inst.f1, inst.f2, inst.A, inst.B, inst.M)
+    if full or inst.N <= SERVE_FULL_PATH_MAX_VERTICES:
+        path, rp, steps = O.reconstruct(inst.d, inst.n, inst.f1, inst.f2, inst.A, inst.B, inst.M)
+        complete = True
+    else:
+        path, rp, steps, complete = O.reconstruct_upto(inst.d, inst.n, inst.f1, inst.f2, inst.A,
+                                                       inst.B, inst.M, SERVE_PREFIX_STEPS)
     dt = time.time() - t0
     assert rp.tuple() == r.tuple()
     return dict(k=k, d=inst.d, n=inst.n, K=inst.meta["K"], M=inst.M, seed=inst.meta["seed"],
                 T=r.T, X=r.X, x=r.x, Y=r.Y, F2=r.F2, counters=r.counters,
-                labels_sha256=labels_sha256(r.labels), path=[int(v) for v in path],
+                labels_sha256=labels_sha256(r.labels), path_complete=bool(complete),
+                path=[int(v) for v in path],
                 resolves=[[int(v) for v in row] for row in steps], oracle_seconds=round(dt, 2))
+
+
+def serve8_whole_path(k):
+    """The whole chain of one serving request, stored on its own."""
+    t0 = time.time()
+    rec = _serve_one(k, full=True)
+    with open(os.path.join(HERE, f"serve8_s51_path{k}.json"), "w") as fh:
+        json.dump(rec, fh, indent=0)
+    print(f"serve8_s51_path{k}: {len(rec['path'])} vertices, {time.time() - t0:.0f} s", flush=True)
 
 
 def make_many(name, fn, items, workers, desc):
@@ -129,5 +155,7 @@ if __name__ == "__main__":
             batch1024(workers)
         elif nm == "serve8":
             serve8(workers)
+        elif nm.startswith("serve8_path"):
+            serve8_whole_path(int(nm[len("serve8_path"):]))
         else:
             make(nm, all_cases[nm])
