@@ -92,6 +92,28 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n,
                   uint32_t *labels, csp_result *out, csp_counters *cnt,
                   int64_t max_cycles, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve, arguments, results and errors as csp_solve_dev, with no device
+ * allocation in the call.  All device state of the solve (edge records,
+ * frontier lists, candidates, the wheel of flows in transit) lives in one
+ * static array of CSP_SCRATCH_BYTES on each GPU, set up by csp_create and
+ * held until the process ends; the barrier and result block are the
+ * context's.  Every call on a GPU shares that array, so calls that overlap
+ * on one GPU race.  Runs only the range-owned kernel.  Errors besides those
+ * of csp_solve_dev: CSP_EINVAL when a range of the lattice does not fit in
+ * LDS, when the lattice's records, lists and candidates leave the wheel
+ * less than 16 flows per bucket of every range, or when a cycle trace is
+ * set; CSP_EOVERFLOW when the flows in transit overflow the wheel carved
+ * from the array (there is no retry with a larger one); CSP_EDEVICE when
+ * the device has no copy of the array. */
+#define CSP_SCRATCH_BYTES (256ull << 20)
+int csp_solve_dev_noalloc(csp_ctx *ctx, int d, int64_t n,
+                          const uint8_t *f1, const uint8_t *f2,
+                          const uint8_t *A, const uint8_t *B, uint32_t M,
+                          uint32_t *labels, csp_result *out, csp_counters *cnt,
+                          int64_t max_cycles, void *stream);
+
 /* Same on host buffers: copies inputs to the device of ctx, solves, copies
  * labels (nullable host uint32 [N]) back.  Synchronous. */
 int csp_solve(csp_ctx *ctx, int d, int64_t n,

@@ -21,6 +21,7 @@ CSP_EDEVICE = -3
 CSP_EOVERFLOW = -4
 CSP_ECANCELED = -5
 CSP_MAX_M = 0x0FFFFFFF
+CSP_SCRATCH_BYTES = 256 << 20
 
 EXPORTED = (
     "csp_create", "csp_destroy", "csp_last_error", "csp_solve_dev", "csp_solve",
@@ -31,6 +32,7 @@ EXPORTED = (
     "csp_reconstruct_log_dev", "csp_solve_graph_dev", "csp_autotune", "csp_autotune_clear",
     "csp_set_batch_target", "csp_autotune_batch", "csp_reconstruct",
     "csp_set_dense_threshold", "csp_tuned_dense_threshold", "csp_last_phase_spread",
+    "csp_solve_dev_noalloc",
 )
 
 
@@ -81,6 +83,8 @@ def _load():
     lib.csp_solve_dev.argtypes = [p, i32, i64, p, p, p, p, u32, p, ctypes.POINTER(csp_result),
                                   ctypes.POINTER(csp_counters), i64, p]
     lib.csp_solve_dev.restype = i32
+    lib.csp_solve_dev_noalloc.argtypes = lib.csp_solve_dev.argtypes
+    lib.csp_solve_dev_noalloc.restype = i32
     lib.csp_solve.argtypes = [p, i32, i64, p, p, p, p, u32, p, ctypes.POINTER(csp_result),
                               ctypes.POINTER(csp_counters)]
     lib.csp_solve.restype = i32
@@ -194,6 +198,19 @@ def csp_solve_dev(ctx, d, n, f1, f2, A, B, M, labels=None, counters=True, max_cy
     rc = lib.csp_solve_dev(ctx, d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), M, _ptr(labels),
                            ctypes.byref(res), ctypes.byref(cnt) if counters else None,
                            max_cycles, _stream(stream))
+    _check(ctx, rc)
+    return res, (cnt if counters else None)
+
+
+def csp_solve_dev_noalloc(ctx, d, n, f1, f2, A, B, M, labels=None, counters=True, max_cycles=0,
+                          stream=None):
+    """As csp_solve_dev; the solve's device state lives in the library's
+    static per-GPU scratch (CSP_SCRATCH_BYTES), so the call allocates nothing."""
+    res = csp_result()
+    cnt = csp_counters()
+    rc = lib.csp_solve_dev_noalloc(ctx, d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), M, _ptr(labels),
+                                   ctypes.byref(res), ctypes.byref(cnt) if counters else None,
+                                   max_cycles, _stream(stream))
     _check(ctx, rc)
     return res, (cnt if counters else None)
 

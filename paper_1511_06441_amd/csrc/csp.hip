@@ -58,6 +58,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -2656,8 +2657,21 @@ size_t rec_bytes(int d) { return d == 1 ? 4 : (d == 2 ? 8 : 16); }
 // host side
 // ---------------------------------------------------------------------------
 
+// Device state of csp_solve_dev_noalloc: one array on every GPU the library
+// runs on, held until the process ends.  Host code never uses this name as
+// an address: each device's copy is reached through the pointer that
+// hipGetSymbolAddress returned for it (scratch_dev).
+static __device__ __align__(256) uint8_t scratch[CSP_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+uint8_t *scratch_dev[SCRATCH_DEVICES] = {};   // per device: address of its copy of scratch
+}  // namespace
+
 struct csp_ctx {
     int device = 0;
+    uint8_t *scratch = nullptr;     // this device's copy of the static scratch (null: unavailable)
     int num_cu = 0;
     int max_blocks[5] = {0, 0, 0, 0, 0};
     unsigned long long wall_khz = 100000;
@@ -3078,6 +3092,18 @@ int csp_create(int device, csp_ctx **out)
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return CSP_EDEVICE; }
     ctx->num_cu = prop.multiProcessorCount;
     ctx->lds_limit = std::max<size_t>(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
+    if (device < SCRATCH_DEVICES) {
+        // once per device, with the device current: its copy of the static
+        // scratch (left null if the runtime cannot give it; only
+        // csp_solve_dev_noalloc needs it and then reports the error)
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        if (!scratch_dev[device]) {
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) scratch_dev[device] = (uint8_t *)ptr;
+            else (void)hipGetLastError();
+        }
+        ctx->scratch = scratch_dev[device];
+    }
     {
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
@@ -3350,6 +3376,118 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
     }
 }
 
+// csp_solve_dev without allocation: the range-owned kernel (the only one the
+// scratch serves) with its edge records, frontier lists, candidate fills,
+// candidates and wheel carved from this device's copy of the static scratch;
+// the barrier and result block stay in the context (allocated when it was
+// created).  Nothing in the scratch has to start at zero: every range packs
+// its records, clears its own fills before the first barrier and writes
+// wheel and candidate entries before anything reads them.  Calls on one GPU
+// share the array, so calls that overlap on one GPU race.
+int solve_noalloc(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2, const uint8_t *A,
+                  const uint8_t *B, uint32_t M, uint32_t *labels, csp_result *out, csp_counters *cnt,
+                  int64_t max_cycles, void *stream)
+{
+    if (!ctx || !out || !f1 || !f2 || !A || !B) return fail(ctx, CSP_EINVAL, "null argument");
+    if (ctx->trace) return fail(ctx, CSP_EINVAL, "the allocation-free solve keeps no cycle trace");
+    if (!ctx->scratch) return fail(ctx, CSP_EDEVICE, "no static scratch on this device");
+    long long N = 0;
+    int rc = check_shape(ctx, d, n, M, N);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+
+    const int path = path_for(ctx, d, N);
+    if (path == 2) return fail(ctx, CSP_EINVAL, "the allocation-free solve runs only the range-owned kernel");
+    LdsPlan plan = plan_lds(ctx, d, n, N, M, blocks_for(ctx, d, N), path);
+    const void *kf = plan.ok ? lds_kernel(d, plan.tile, false) : nullptr;
+    if (plan.ok && hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds) != hipSuccess)
+        plan.ok = false;
+    int nb = 0;
+    if (plan.ok && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kf, BLOCK, plan.lds) != hipSuccess ||
+                    nb * ctx->num_cu < plan.G))
+        plan.ok = false;
+    if (!plan.ok) return fail(ctx, CSP_EINVAL, "a range of this lattice does not fit in LDS");
+    const int G = plan.G;
+    ctx->last_path = 1;
+
+    // layout in the scratch: records | lists | fills | candidates | wheel
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const unsigned long long NO = plan.tile ? 2ull * d : 2ull * plan.K + 1;
+    const unsigned long long cand_max = 2ull * d * (unsigned long long)plan.c;
+    const unsigned long long ccap =
+        plan.tile ? (unsigned long long)n * plan.ty
+                  : std::min<unsigned long long>(cand_max, std::max<unsigned long long>(4096ull, plan.c / 2));
+    const size_t off_lists = up((size_t)(plan.c * G) * rec_bytes(d));
+    const size_t off_pub = off_lists + up((size_t)(plan.c * G) * 4);
+    const size_t off_cand = off_pub + up((size_t)2 * G * NOMAX * 4);
+    const size_t off_pool = off_cand + up((size_t)(2ull * G * NO * ccap * 8));
+    // the wheel gets the rest; at least 16 flows per bucket of every range
+    if (off_pool + (size_t)G * MAXW * 16 * 8 > (size_t)CSP_SCRATCH_BYTES)
+        return fail(ctx, CSP_EINVAL, "lattice too large for the allocation-free solve (CSP_SCRATCH_BYTES)");
+    const unsigned long long pool = ((size_t)CSP_SCRATCH_BYTES - off_pool) / 8;
+
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(BLOCK), 0, s, ctx->ctl);
+    RJ p;
+    fill_job(p, d, n, N, plan, f1, f2, A, B, M);
+    p.dense_thr = dense_for(ctx, d, N, plan.c);
+    p.rec = ctx->scratch;
+    p.lists = reinterpret_cast<unsigned *>(ctx->scratch + off_lists);
+    p.pubc = reinterpret_cast<unsigned *>(ctx->scratch + off_pub);
+    p.cand = reinterpret_cast<uint2 *>(ctx->scratch + off_cand);
+    p.cand_cap = (unsigned)ccap;
+    p.pool = reinterpret_cast<uint2 *>(ctx->scratch + off_pool);
+    p.pool_flows = pool;
+    p.bar = &ctx->ctl->rbar;
+    p.out = &ctx->ctl->rout;
+    p.labels_out = labels;
+    p.max_cycles = max_cycles;
+    p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+    p.prof = ctx->prof;
+    void *args[] = {&p};
+    HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
+    HIP_TRY(hipLaunchCooperativeKernel(kf, dim3(G), dim3(BLOCK), args, (unsigned)plan.lds, s), "solve launch");
+    HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
+    {
+        const size_t lo = offsetof(Ctl, xkey), hi = offsetof(Ctl, rbar);
+        HIP_TRY(hipMemcpyAsync(reinterpret_cast<uint8_t *>(ctx->h_ctl) + lo,
+                               reinterpret_cast<const uint8_t *>(ctx->ctl) + lo, hi - lo, hipMemcpyDeviceToHost, s),
+                "ctl copy");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "solve");
+    const Out &o = ctx->h_ctl->rout;
+    if (o.status == ST_INVAL) return fail(ctx, CSP_EINVAL, "an edge has f1 or f2 equal to 0, or A and B overlap");
+    if (o.status == ST_OVERFLOW)
+        return fail(ctx, CSP_EOVERFLOW, "flows in transit overflow the allocation-free solve's wheel");
+    if (o.status == ST_CANCELED) return fail(ctx, CSP_ECANCELED, "cycle cap reached");
+    if (o.status == ST_BROKEN) return fail(ctx, CSP_EDEVICE, "grid barrier timed out or inconsistent result");
+    if (o.status != ST_DONE) return fail(ctx, CSP_EDEVICE, "solve did not finish");
+    HIP_TRY(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1), "event time");
+    for (int i = 0; i < 8; ++i) {
+        ctx->last_prof[i] = o.prof[i];
+        ctx->last_psum[i] = ctx->prof == 2 ? o.psum[i] : 0;
+        ctx->last_pmax[i] = ctx->prof == 2 ? o.pmax[i] : 0;
+    }
+    ctx->last_spread_ranges = G;
+    ctx->last_trace_rows = 0;
+    ctx->last_xrec = -1;
+    out->T = o.res[0];
+    out->X = o.res[1];
+    out->x = o.res[2];
+    out->Y = o.res[3];
+    out->F2 = o.res[4];
+    if (cnt) {
+        cnt->C = (int64_t)o.ctr[0];
+        cnt->U = (int64_t)o.ctr[1];
+        cnt->D = (int64_t)o.ctr[2];
+        cnt->E = (int64_t)o.ctr[3];
+        cnt->R = (int64_t)o.ctr[4];
+        cnt->P = (int64_t)o.ctr[5];
+        cnt->I = (int64_t)o.ctr[6];
+    }
+    return CSP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3359,6 +3497,13 @@ int csp_solve_dev(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
                   csp_result *out, csp_counters *cnt, int64_t max_cycles, void *stream)
 {
     return solve_impl(ctx, d, n, f1, f2, A, B, M, labels, out, cnt, max_cycles, stream, false);
+}
+
+int csp_solve_dev_noalloc(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t *f2,
+                          const uint8_t *A, const uint8_t *B, uint32_t M, uint32_t *labels,
+                          csp_result *out, csp_counters *cnt, int64_t max_cycles, void *stream)
+{
+    return solve_noalloc(ctx, d, n, f1, f2, A, B, M, labels, out, cnt, max_cycles, stream);
 }
 
 int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int32_t *nbr, const uint8_t *f1,

@@ -32,6 +32,8 @@ def test_header_constants_match_binding():
         assert m and int(m.group(1)) == getattr(csp, nm), nm
     m = re.search(r"#define CSP_MAX_M (0x[0-9A-Fa-f]+)u", text)
     assert int(m.group(1), 16) == csp.CSP_MAX_M
+    m = re.search(r"#define CSP_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == csp.CSP_SCRATCH_BYTES
 
 
 def test_result_struct_layout():
