@@ -103,6 +103,13 @@ struct BarHdr {
     unsigned long long res[2][16]; // sums and maximum of the last two barriers
     int broken;
     int pad[31];
+    // gang_or (the cycle loop's barrier): arrival words of the groups and of
+    // the root by barrier parity (word 0 of each line), per-barrier sums for
+    // member 0 (words 0-2 of a ring of four lines) and the best B key
+    unsigned long long ow[2][16][16];
+    unsigned long long oroot[2][16];
+    unsigned long long ring[4][16][3][16];   // [barrier & 3][group][sum] (word 0 of each line)
+    unsigned long long bkey[16];
 };
 
 __host__ __device__ inline size_t bar_bytes(unsigned g) { return sizeof(BarHdr) + (size_t)2 * g * 128; }
@@ -801,18 +808,6 @@ __device__ __forceinline__ void vm_drain()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__device__ __forceinline__ void release_(bool lite)
-{
-    if (lite) vm_drain();
-    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-}
-
-__device__ __forceinline__ void acquire_(bool lite)
-{
-    if (lite) __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
 // Tree barrier among the g workgroups of a gang (member m is the caller)
 // that combines one Comb per member.  Members write their Comb to a private
 // slot line, publish with an agent-scope release fence and count themselves
@@ -822,21 +817,13 @@ __device__ __forceinline__ void acquire_(bool lite)
 // epoch, into every member's flag line.  Waiters spin on their own line; a
 // wait that outlasts `limit` wall-clock ticks marks the gang broken and the
 // call returns false, so a logic error drains the gang instead of hanging.
-//
-// lite: everything the members exchange around this barrier is stored and
-// loaded with agent-scope atomics (the barrier's own words, and the caller's
-// candidates and their fills), which are coherent across the XCDs' L2 caches
-// by themselves.  The barrier then only waits for each wave's accesses to
-// complete before publishing, instead of writing back and invalidating the
-// L2 (which would also evict the edge records and wheel lines each
-// workgroup keeps reusing).
+// The cycle loop uses gang_or instead; this one publishes the plain stores
+// made before it (edge records, fills cleared at initialisation, results).
 __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
-                             const Comb &mine, Comb &out, bool need_rest, unsigned long long *tpub = nullptr,
-                             bool lite = false)
+                             const Comb &mine, Comb &out, bool need_rest, unsigned long long *tpub = nullptr)
 {
     __shared__ int s_ok;
     __shared__ unsigned long long s_o[5];
-    if (lite) vm_drain();
     __syncthreads();
     ++epoch;
     if (g == 1) {
@@ -857,7 +844,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
             st64(&sl[2], mine.s1);
             st64(&sl[3], mine.s2);
             st64(&sl[4], mine.mx);
-            release_(lite);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned a = __hip_atomic_fetch_add(&bh->grp[grp][0], 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             leader = a == members - 1;
@@ -865,7 +852,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
         }
         leader = __shfl(leader, 0);
         if (leader) {
-            acquire_(lite);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             unsigned mn = 0xFFFFFFFFu, orf = 0;
             unsigned long long s0 = 0, s1 = 0, s2 = 0, mx = 0;
             for (unsigned j = lane; j < members; j += 64) {
@@ -888,7 +875,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
                 st64(&gs[2], s1);
                 st64(&gs[3], s2);
                 st64(&gs[4], mx);
-                release_(lite);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 const unsigned rr = __hip_atomic_fetch_add(&bh->root[0], 1u, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);
                 releaser = rr == ngrp - 1;
@@ -896,7 +883,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
             }
             releaser = __shfl(releaser, 0);
             if (releaser) {
-                acquire_(lite);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 mn = 0xFFFFFFFFu;
                 orf = 0;
                 s0 = s1 = s2 = mx = 0;
@@ -920,7 +907,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
                     st64(&rs[2], s2);
                     st64(&rs[3], mx);
                 }
-                release_(lite);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 const unsigned long long w = ((unsigned long long)epoch << 32) |
                                              ((unsigned long long)(orf >> 28) << 16) | (mn < 0xFFFFu ? mn : 0xFFFFu);
                 for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], w);
@@ -940,7 +927,7 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
                     break;
                 }
             }
-            acquire_(lite);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
             const unsigned mn16 = (unsigned)(w & 0xFFFFu), orf = (unsigned)((w >> 16) & 0xFu) << 28;
             s_o[0] = (unsigned long long)(mn16 == 0xFFFFu ? 0xFFFFFFFFu : mn16) | ((unsigned long long)orf << 32);
@@ -959,6 +946,172 @@ __device__ bool gang_combine(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch
     out.s2 = s_o[3];
     out.mx = s_o[4];
     out.rest = bh->res[epoch & 1];
+    const bool ok = s_ok != 0;
+    __syncthreads();
+    return ok;
+}
+
+// Barrier of the cycle loop.  Everything the members exchange around it
+// (the words below, the caller's candidates and their fills) goes through
+// agent-scope atomics, which are coherent across the XCDs' L2 caches by
+// themselves, so it writes back and invalidates no cache; each wave only
+// waits for its own accesses to complete before the workgroup arrives.
+//
+// Arrival is one fetch-or per level.  A member's word holds its arrival bit
+// (bits 0-31), the four flag bits (32-35), a "far" bit (36) and the bit of
+// its next event delta when that is 1..27 (bits 37-63); groups are up to 32
+// consecutive members.  The fetch-or that completes a group's arrival bits
+// forwards the or of the group's words (with the group's own arrival bit)
+// to the root word, and the one that completes the root releases every
+// member with (epoch, flags, least delta).  A member whose next delta is
+// 28 or more sets "far" and first writes the delta, tagged with the epoch,
+// to its slot line; only when no member has a near delta does the releaser
+// read the slots.  So from the last member's arrival to everyone's wake-up
+// there are two atomic round trips and one store-to-load delay.
+//
+// Sums (s0, s1, s2) and the B key (mx) bypass the barrier: the caller
+// (gang_or_post) adds its sums to this barrier's line of a ring of four and
+// raises the B key with an atomic maximum as soon as they are known, well
+// before it arrives; member 0 reads the sums after the barrier (out.rest,
+// final then) and clears the line, and everyone reads the B key after a
+// barrier whose flags carry SF_BHIT.  Member 0 clears the ring lines, the B
+// key and the arrival words at the start of each solve, before the solve's
+// first (fully fenced) barrier.  A wait beyond `limit` ticks marks the gang
+// broken, as in gang_combine.
+constexpr unsigned OR_FAR = 36, OR_D0 = 37, OR_ND = 27;
+
+__device__ __forceinline__ unsigned or_group_size(unsigned g) { return g <= 256 ? 16u : 32u; }
+
+// What member m contributes to the next gang_or outside its arrival word:
+// its sums, added to its group's lines of that barrier (so at most 32
+// members add to one word), and its B key.
+__device__ __forceinline__ void gang_or_post(BarHdr *bh, unsigned g, unsigned m, unsigned epoch,
+                                             unsigned long long s0, unsigned long long s1, unsigned long long s2,
+                                             unsigned long long mx)
+{
+    if (g == 1) return;
+    unsigned long long(*ln)[16] = bh->ring[(epoch + 1) & 3][m / or_group_size(g)];
+    if (s0) __hip_atomic_fetch_add(&ln[0][0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (s1) __hip_atomic_fetch_add(&ln[1][0], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (s2) __hip_atomic_fetch_add(&ln[2][0], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (mx) __hip_atomic_fetch_max(&bh->bkey[0], mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Member 0, after gang_or with epoch e: the sums of that barrier over all
+// groups (wave 0), and the ring lines cleared for barrier e + 4.
+__device__ __forceinline__ void gang_or_sums(BarHdr *bh, unsigned g, unsigned e, unsigned long long &s0,
+                                             unsigned long long &s1, unsigned long long &s2)
+{
+    const unsigned lane = threadIdx.x & 63u, ngr = (g + or_group_size(g) - 1) / or_group_size(g);
+    unsigned long long v[3] = {0, 0, 0};
+    if (lane < ngr) {
+        unsigned long long(*ln)[16] = bh->ring[e & 3][lane];
+        for (int k = 0; k < 3; ++k) {
+            v[k] = ld64(&ln[k][0]);
+            st64(&ln[k][0], 0ull);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], o);
+    s0 = v[0];
+    s1 = v[1];
+    s2 = v[2];
+}
+
+__device__ bool gang_or(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
+                        const Comb &mine, Comb &out, unsigned long long *tpub = nullptr)
+{
+    __shared__ int s_ok;
+    __shared__ unsigned long long s_o[2];
+    const unsigned e = epoch + 1;
+    if (g > 1 && threadIdx.x == 0) {
+        if (mine.mn != 0xFFFFFFFFu && mine.mn > OR_ND)
+            st64(&bar_slot(bh, m)[8], ((unsigned long long)e << 32) | mine.mn);
+    }
+    vm_drain();
+    __syncthreads();
+    epoch = e;
+    if (g == 1) {
+        out = mine;
+        out.rest = nullptr;
+        return true;
+    }
+    if (threadIdx.x < 64) {
+        const unsigned lane = threadIdx.x;
+        const unsigned MG = or_group_size(g);                  // members per group
+        const unsigned ngr = (g + MG - 1) / MG;
+        const unsigned grp = m / MG, gsz = min(MG, g - grp * MG);
+        const unsigned long long tag = (unsigned long long)e << 32;
+        int ok = 1;
+        const unsigned long long t0 = wall_clock64();
+        if (tpub && lane == 0) *tpub = t0;
+        unsigned long long comb = 0, rel = 2;  // rel: 2 not the releaser, 1 releaser reading far deltas, 0 releaser
+        if (lane == 0) {
+            unsigned long long w = (1ull << (m - grp * MG)) | ((unsigned long long)(mine.orf >> 28) << 32);
+            if (mine.mn != 0xFFFFFFFFu) w |= mine.mn <= OR_ND ? 1ull << (OR_D0 + mine.mn - 1) : 1ull << OR_FAR;
+            unsigned long long *gw = &bh->ow[e & 1][grp][0];
+            const unsigned long long full_g = gsz == 64 ? ~0ull : (1ull << gsz) - 1;
+            const unsigned long long og = __hip_atomic_fetch_or(gw, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | w;
+            if ((og & 0xFFFFFFFFull) == full_g) {
+                // last of its group: forward the group to the root
+                const unsigned long long rw = (og & ~0xFFFFFFFFull) | (1ull << grp);
+                const unsigned long long full_r = (1ull << ngr) - 1;
+                const unsigned long long orr =
+                    __hip_atomic_fetch_or(&bh->oroot[e & 1][0], rw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | rw;
+                if ((orr & 0xFFFFFFFFull) == full_r) {
+                    // last group: combine and release.  The arrival words of
+                    // this parity are cleared for the barrier after next.
+                    for (unsigned k = 0; k < ngr; ++k) st64(&bh->ow[e & 1][k][0], 0ull);
+                    st64(&bh->oroot[e & 1][0], 0ull);
+                    const unsigned long long near = (orr >> OR_D0) & ((1ull << OR_ND) - 1);
+                    unsigned mn = 0xFFFFFFFFu;
+                    if (near) mn = (unsigned)__builtin_ctzll(near) + 1;
+                    rel = ((orr >> OR_FAR) & 1ull) && !near ? 1 : 0;
+                    comb = ((unsigned long long)((orr >> 32) & 0xFull) << 32) | mn;
+                }
+            }
+        }
+        // the releaser reads the far deltas when there is no near one
+        rel = __shfl(rel, 0);
+        if (rel != 2) {
+            comb = __shfl(comb, 0);
+            unsigned mn = (unsigned)comb, orf4 = (unsigned)(comb >> 32);
+            if (rel == 1) {
+                unsigned fm = 0xFFFFFFFFu;
+                for (unsigned i = lane; i < g; i += 64) {
+                    const unsigned long long v = ld64(&bar_slot(bh, i)[8]);
+                    if ((v & 0xFFFFFFFF00000000ull) == tag) fm = min(fm, (unsigned)v);
+                }
+                for (int o = 32; o > 0; o >>= 1) fm = min(fm, (unsigned)__shfl_xor(fm, o));
+                mn = fm;
+            }
+            const unsigned long long rw = tag | ((unsigned long long)orf4 << 16) | (mn < 0xFFFFu ? mn : 0xFFFFu);
+            for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], rw);
+        }
+        if (lane == 0) {
+            unsigned long long *fl = bar_flag(bh, g, m);
+            unsigned long long w;
+            while (((w = ld64(&fl[0])) >> 32) < (unsigned long long)e) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - t0 > limit) {
+                    __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+            if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+            const unsigned mn16 = (unsigned)(w & 0xFFFFu), orf = (unsigned)((w >> 16) & 0xFu) << 28;
+            s_o[0] = (unsigned long long)(mn16 == 0xFFFFu ? 0xFFFFFFFFu : mn16) | ((unsigned long long)orf << 32);
+            s_o[1] = (orf & SF_BHIT) ? ld64(&bh->bkey[0]) : 0;
+            s_ok = ok;
+        }
+    }
+    __syncthreads();
+    out.mn = (unsigned)s_o[0];
+    out.orf = (unsigned)(s_o[0] >> 32);
+    out.s0 = out.s1 = out.s2 = 0;
+    out.mx = s_o[1];
+    out.rest = nullptr;
     const bool ok = s_ok != 0;
     __syncthreads();
     return ok;
@@ -1435,6 +1588,18 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         log_improved(0, nlist, true);
     }
 
+    if (lead) {
+        // gang_or's arrival words, sums ring and B key start from zero in
+        // every solve (published by the fully fenced barrier below)
+        BarHdr *bh = p.bar;
+        for (unsigned i = tid; i < 2 * 16 + 2 + 4 * 16 * 3 + 1; i += BLOCK) {
+            unsigned long long *w = i < 32 ? &bh->ow[i / 16][i % 16][0]
+                                    : i < 34 ? &bh->oroot[i - 32][0]
+                                    : i < 34 + 192 ? &bh->ring[(i - 34) / 48][(i - 34) / 3 % 16][(i - 34) % 3][0]
+                                                   : &bh->bkey[0];
+            st64(w, 0ull);
+        }
+    }
     int status = ST_RUNNING;
     unsigned W = 2;
     RunRes rr;
@@ -1598,7 +1763,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         mine.s1 = nlist;
         mine.s2 = transit;
         mine.mx = s_xkey;
-        if (!gang_combine(p.bar, G, r, epoch, p.wait_limit, mine, all, false, p.prof ? &s_tpub : nullptr, true)) {
+        if (!gang_or(p.bar, G, r, epoch, p.wait_limit, mine, all, p.prof ? &s_tpub : nullptr)) {
             status = ST_BROKEN;
             break;
         }
@@ -1610,12 +1775,12 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             ph_t = now_;
         }
 
+        // the counters' sums are needed by the lead only; it clears the
+        // ring line they came in for a later barrier
+        unsigned long long a0 = all.s0, a1 = all.s1, a2 = all.s2;
+        if (lead && tid < 64 && G > 1) gang_or_sums(p.bar, G, epoch, a0, a1, a2);
         if (all.orf & SF_OVER) { status = ST_OVERFLOW; break; }
         if (cyc > 0 && lead && tid == 0) {
-            // the counters' sums are needed by the lead only
-            const unsigned long long a0 = all.rest ? ld64(&all.rest[0]) : all.s0;
-            const unsigned long long a1 = all.rest ? ld64(&all.rest[1]) : all.s1;
-            const unsigned long long a2 = all.rest ? ld64(&all.rest[2]) : all.s2;
             s_lc[0] += a0 > 0 ? 1 : 0;
             s_lc[2] = a1 > s_lc[2] ? a1 : s_lc[2];
             s_lc[1] = a2 > s_lc[1] ? a2 : s_lc[1];
@@ -1845,6 +2010,8 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             }
             __syncthreads();
             transit = s_sum;
+            // the next barrier's sums and B key, long before it
+            if (tid == 0) gang_or_post(p.bar, G, r, epoch, F, nlist, transit, s_xkey);
             if constexpr (LOG) log_improved(t, nlist, false);
         }
         PHASE4(3);
