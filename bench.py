@@ -313,6 +313,40 @@ def run_recon(args):
     solver.close()
 
 
+def run_micro(args):
+    """The device limits behind the cycle's shape: copy bandwidth, scattered
+    atomicMax rate, scattered 16-byte loads (the sending step's edge
+    records) and the two barriers (the cycle loop's, and the fully fenced
+    one with dirty lines to write back)."""
+    import torch
+    from paper_1511_06441_amd import csp
+
+    solver = csp.Solver(0)
+    stream = torch.cuda.current_stream()
+    mb = lambda *a: csp.csp_microbench(solver.ctx, *a, stream=stream)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    mb(csp.MB_COPY, 1 << 30, 1)
+    out = {"copy_1GiB_GBps": mb(csp.MB_COPY, 1 << 30, 10)[0]}
+    mb(csp.MB_ATOMIC, 1 << 24, 1 << 24)
+    out["atomicmax_scattered_Gps"] = {"64MiB": mb(csp.MB_ATOMIC, 1 << 28, 1 << 24)[0],
+                                      "1GiB": mb(csp.MB_ATOMIC, 1 << 28, 1 << 28)[0]}
+    out["record_loads"] = {}
+    for nr in (1024, 3400, 6800):
+        mb(csp.MB_LOADS, nr, 10)
+        g, us = mb(csp.MB_LOADS, nr, 400)
+        out["record_loads"][f"{nr}_per_cu"] = {"G_loads_per_s": g, "us_per_round": us}
+    out["barrier_us"] = {}
+    for dirty in (0, 64, 256):
+        mb(csp.MB_BARRIER, 100, cus, dirty)
+        a, b2 = mb(csp.MB_BARRIER, 2000, cus, dirty)
+        out["barrier_us"][f"{cus}wg_dirty{dirty}KiB"] = {"cycle_loop": a, "fenced": b2}
+    line = {"metric": "device micro-benchmarks", "value": out["copy_1GiB_GBps"], "unit": "GB/s (copy)",
+            "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True, "dtype": "u32",
+            "data": "synthetic", "config": {"workload": "micro", "cus": cus}, "micro": out}
+    print(json.dumps(line), flush=True)
+    solver.close()
+
+
 def algorithmic_bytes(N, c, L=4):
     """Bytes the method must move for one solve with L-byte labels (label
     init, own label per improvement, f1+f2+neighbour label per test, one flow
@@ -426,7 +460,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cube256", choices=sorted(WORKLOADS) + ["batch1024", "serve", "recon", "graph128"])
+    ap.add_argument("--workload", default="cube256",
+                    choices=sorted(WORKLOADS) + ["batch1024", "serve", "recon", "graph128", "micro"])
     ap.add_argument("--batch-count", type=int, default=1024)
     ap.add_argument("--plain", action="store_true", help="batch workload: also time sequential plain launches")
     ap.add_argument("--serve-count", type=int, default=8)
@@ -455,6 +490,9 @@ def main():
         return
     if args.workload == "graph128":
         run_graph(args)
+        return
+    if args.workload == "micro":
+        run_micro(args)
         return
 
     import torch

@@ -309,6 +309,24 @@ int csp_last_phase_us(const csp_ctx *ctx, double *us);
  * building I_t.  Zero when the last solve took the global-label kernel. */
 int csp_last_phase_spread(const csp_ctx *ctx, double *mean, double *max);
 
+/* Micro-benchmarks of the device resources the cycle is bound by (no
+ * solve; timed with HIP events on `stream`; buffers from the context).
+ *   kind 0: copy p0 bytes (a multiple of 16) device to device, p1 times;
+ *           r[0] = GB/s of bytes read plus bytes written.
+ *   kind 1: p0 32-bit atomic maxima at hashed positions of p1 words (a power
+ *           of two); r[0] = G atomics/s.
+ *   kind 2: one workgroup per CU, each doing p0 16-byte loads at hashed
+ *           positions of its own 1 MiB slab per round, p1 rounds (the edge
+ *           record fetches of the sending step); r[0] = G loads/s, r[1] = us
+ *           per round.
+ *   kind 3: p0 barriers among p1 (2..CUs) workgroups of a cooperative launch:
+ *           r[0] = us per barrier of the cycle loop's kind; r[1] = us per
+ *           fully fenced barrier after every member wrote p2 KiB with plain
+ *           stores.  Each barrier's combined minimum is checked (CSP_EDEVICE
+ *           if one is wrong).
+ * CSP_EINVAL for an unknown kind or sizes out of range. */
+int csp_microbench(csp_ctx *ctx, int kind, int64_t p0, int64_t p1, int64_t p2, double *r, void *stream);
+
 /* ---- Serving: continuous batching of solves and reconstructions --------
  *
  * A server runs one persistent kernel whose workers (one workgroup per CU)

@@ -32,7 +32,7 @@ EXPORTED = (
     "csp_reconstruct_log_dev", "csp_solve_graph_dev", "csp_autotune", "csp_autotune_clear",
     "csp_set_batch_target", "csp_autotune_batch", "csp_reconstruct",
     "csp_set_dense_threshold", "csp_tuned_dense_threshold", "csp_last_phase_spread",
-    "csp_solve_dev_noalloc",
+    "csp_solve_dev_noalloc", "csp_microbench",
 )
 
 
@@ -85,6 +85,8 @@ def _load():
     lib.csp_solve_dev.restype = i32
     lib.csp_solve_dev_noalloc.argtypes = lib.csp_solve_dev.argtypes
     lib.csp_solve_dev_noalloc.restype = i32
+    lib.csp_microbench.argtypes = [p, i32, i64, i64, i64, ctypes.POINTER(ctypes.c_double), p]
+    lib.csp_microbench.restype = i32
     lib.csp_solve.argtypes = [p, i32, i64, p, p, p, p, u32, p, ctypes.POINTER(csp_result),
                               ctypes.POINTER(csp_counters)]
     lib.csp_solve.restype = i32
@@ -213,6 +215,16 @@ def csp_solve_dev_noalloc(ctx, d, n, f1, f2, A, B, M, labels=None, counters=True
                                    max_cycles, _stream(stream))
     _check(ctx, rc)
     return res, (cnt if counters else None)
+
+
+MB_COPY, MB_ATOMIC, MB_LOADS, MB_BARRIER = 0, 1, 2, 3
+
+
+def csp_microbench(ctx, kind, p0, p1, p2=0, stream=None):
+    """Device micro-benchmark (include/csp.h): returns its two result slots."""
+    r = (ctypes.c_double * 2)()
+    _check(ctx, lib.csp_microbench(ctx, kind, p0, p1, p2, r, _stream(stream)))
+    return r[0], r[1]
 
 
 def csp_solve(ctx, d, n, f1, f2, A, B, M, labels=None):

@@ -2799,6 +2799,99 @@ __global__ void __launch_bounds__(BLOCK) k_graph(GJ p)
 }
 
 // Clear the quit bit and the watcher flag before a serving launch.
+// ---------------------------------------------------------------------------
+// Micro-benchmarks of the device resources the cycle is bound by (csp_microbench)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned mb_hash(unsigned x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void __launch_bounds__(256) k_mb_copy(const uint4 *src, uint4 *dst, unsigned long long n)
+{
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull)
+        dst[i] = src[i];
+}
+
+// n atomic maxima at hashed positions of an array of `words` (a power of two)
+__global__ void __launch_bounds__(256) k_mb_atomic(unsigned *a, unsigned long long words, unsigned long long n)
+{
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull)
+        atomicMax(&a[mb_hash((unsigned)i) & (words - 1)], (unsigned)i);
+}
+
+// per workgroup and round, nr 16-byte loads at hashed positions of its own
+// slab of 65,536 records (1 MiB), four in flight per thread
+__global__ void __launch_bounds__(BLOCK) k_mb_loads(const uint4 *rec, int nr, int rounds, unsigned *sink)
+{
+    const unsigned tid = threadIdx.x, r = blockIdx.x;
+    const uint4 *my = rec + (size_t)r * 65536;
+    unsigned acc = 0;
+    for (int it = 0; it < rounds; ++it) {
+        for (int j0 = (int)tid; j0 < nr; j0 += BLOCK * 4) {
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * BLOCK;
+                if (j < nr) v[u] = my[mb_hash((unsigned)(j * 977 + it * 131) + r) & 65535u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j0 + u * BLOCK < nr) acc ^= v[u].x ^ v[u].w;
+        }
+        __syncthreads();
+    }
+    if (acc == 0x9E3779B9u) sink[0] = acc;      // keeps the loads
+}
+
+// `iters` barriers among the grid: kind 0 the cycle loop's (gang_or), kind 1
+// the fully fenced tree (gang_combine) after each member wrote `dirty_words`
+// words of its own region with plain stores.  Every barrier's combined
+// minimum is checked; a wrong one marks the gang broken.
+__global__ void __launch_bounds__(BLOCK) k_mb_barrier(BarHdr *bh, int kind, int iters, unsigned *dirty,
+                                                      unsigned long long dirty_words, unsigned long long limit)
+{
+    const unsigned G = gridDim.x, m = blockIdx.x;
+    unsigned epoch = 0;
+    if (m == 0) {
+        for (unsigned i = threadIdx.x; i < 2 * 16 + 2 + 4 * 16 * 3 + 1; i += BLOCK) {
+            unsigned long long *w = i < 32 ? &bh->ow[i / 16][i % 16][0]
+                                    : i < 34 ? &bh->oroot[i - 32][0]
+                                    : i < 34 + 192 ? &bh->ring[(i - 34) / 48][(i - 34) / 3 % 16][(i - 34) % 3][0]
+                                                   : &bh->bkey[0];
+            st64(w, 0ull);
+        }
+    }
+    Comb mine, all;
+    mine.orf = 0;
+    mine.s0 = mine.s1 = mine.s2 = mine.mx = 0;
+    mine.mn = 0xFFFFFFFFu;
+    if (!gang_combine(bh, G, m, epoch, limit, mine, all, false)) return;
+    for (int it = 0; it < iters; ++it) {
+        // member (it mod G) has the least delta, 1 + (it mod 5); the others 30
+        mine.mn = m == (unsigned)it % G ? 1u + (unsigned)it % 5u : 30u;
+        bool ok;
+        if (kind == 0) {
+            ok = gang_or(bh, G, m, epoch, limit, mine, all);
+        } else {
+            unsigned *d = dirty + (size_t)m * dirty_words;
+            for (unsigned long long i = threadIdx.x; i < dirty_words; i += BLOCK) d[i] = (unsigned)it;
+            ok = gang_combine(bh, G, m, epoch, limit, mine, all, false);
+        }
+        if (!ok) return;
+        if (all.mn != 1u + (unsigned)it % 5u) {
+            if (threadIdx.x == 0) __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+    }
+}
+
 __global__ void k_serve_reset(unsigned long long *state, unsigned *watch)
 {
     *state &= ~SRV_QUIT;
@@ -3919,6 +4012,96 @@ int csp_last_kernel_ms(const csp_ctx *ctx, float *ms)
     if (!ctx || !ms) return CSP_EINVAL;
     *ms = ctx->last_ms;
     return ctx->last_ms < 0 ? CSP_EINVAL : CSP_OK;
+}
+
+int csp_microbench(csp_ctx *ctx, int kind, int64_t p0, int64_t p1, int64_t p2, double *r, void *stream)
+{
+    if (!ctx || !r) return fail(ctx, CSP_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    float ms = 0.f;
+    auto timed = [&](auto launch) -> int {
+        HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
+        launch();
+        HIP_TRY(hipGetLastError(), "microbenchmark launch");
+        HIP_TRY(hipEventRecord(ctx->ev1, s), "event");
+        HIP_TRY(hipEventSynchronize(ctx->ev1), "microbenchmark");
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "event time");
+        return CSP_OK;
+    };
+    const unsigned nb = (unsigned)ctx->num_cu * 8;
+    int rc = CSP_OK;
+    if (kind == 0) {
+        // copy p0 bytes (a multiple of 16), p1 times; bytes read plus written per second
+        if (p0 < 16 || p0 % 16 || p1 < 1) return fail(ctx, CSP_EINVAL, "copy size");
+        rc = grow(ctx, &ctx->arena, ctx->arena_cap, (size_t)p0 * 2, "microbenchmark buffer");
+        if (rc) return rc;
+        uint4 *a = reinterpret_cast<uint4 *>(ctx->arena), *b = a + p0 / 16;
+        hipLaunchKernelGGL(k_mb_copy, dim3(nb), dim3(256), 0, s, (const uint4 *)b, a, (unsigned long long)(p0 / 16));
+        rc = timed([&] {
+            for (int64_t k = 0; k < p1; ++k)
+                hipLaunchKernelGGL(k_mb_copy, dim3(nb), dim3(256), 0, s, (const uint4 *)a, b, (unsigned long long)(p0 / 16));
+        });
+        if (rc) return rc;
+        r[0] = 2.0 * (double)p0 * (double)p1 / (ms * 1e-3) / 1e9;
+    } else if (kind == 1) {
+        // p0 atomic maxima over p1 words (a power of two)
+        if (p0 < 1 || p1 < 1 || (p1 & (p1 - 1))) return fail(ctx, CSP_EINVAL, "atomic counts");
+        rc = grow(ctx, &ctx->arena, ctx->arena_cap, (size_t)p1 * 4, "microbenchmark buffer");
+        if (rc) return rc;
+        unsigned *a = reinterpret_cast<unsigned *>(ctx->arena);
+        hipLaunchKernelGGL(k_mb_atomic, dim3(nb), dim3(256), 0, s, a, (unsigned long long)p1, (unsigned long long)p1);
+        rc = timed([&] {
+            hipLaunchKernelGGL(k_mb_atomic, dim3(nb), dim3(256), 0, s, a, (unsigned long long)p1, (unsigned long long)p0);
+        });
+        if (rc) return rc;
+        r[0] = (double)p0 / (ms * 1e-3) / 1e9;
+    } else if (kind == 2) {
+        // one workgroup per CU, p0 scattered 16-byte loads each per round, p1 rounds
+        if (p0 < 1 || p1 < 1) return fail(ctx, CSP_EINVAL, "load counts");
+        const size_t words = (size_t)ctx->num_cu * 65536 * 16 + 64;
+        rc = grow(ctx, &ctx->arena, ctx->arena_cap, words, "microbenchmark buffer");
+        if (rc) return rc;
+        HIP_TRY(hipMemsetAsync(ctx->arena, 1, words, s), "fill");
+        const uint4 *rec = reinterpret_cast<const uint4 *>(ctx->arena);
+        unsigned *sink = reinterpret_cast<unsigned *>(ctx->arena + (size_t)ctx->num_cu * 65536 * 16);
+        rc = timed([&] {
+            hipLaunchKernelGGL(k_mb_loads, dim3((unsigned)ctx->num_cu), dim3(BLOCK), 0, s, rec, (int)p0, (int)p1, sink);
+        });
+        if (rc) return rc;
+        r[0] = (double)ctx->num_cu * (double)p0 * (double)p1 / (ms * 1e-3) / 1e9;
+        r[1] = 1000.0 * ms / (double)p1;
+    } else if (kind == 3) {
+        // p0 barriers among p1 workgroups: the cycle loop's, then the fully
+        // fenced one with p2 KiB of dirty lines per member
+        if (p0 < 1 || p1 < 2 || p1 > ctx->num_cu || p2 < 0) return fail(ctx, CSP_EINVAL, "barrier counts");
+        const unsigned G = (unsigned)p1;
+        const size_t bar = (bar_bytes(G) + 255) & ~(size_t)255;
+        const unsigned long long dw = (unsigned long long)p2 * 256;
+        rc = grow(ctx, &ctx->arena, ctx->arena_cap, bar + (size_t)G * dw * 4 + 256, "microbenchmark buffer");
+        if (rc) return rc;
+        BarHdr *bh = reinterpret_cast<BarHdr *>(ctx->arena);
+        unsigned *dirty = reinterpret_cast<unsigned *>(ctx->arena + bar);
+        const unsigned long long limit = ctx->wall_khz * 1000ull * 10ull;
+        for (int kd = 0; kd < 2; ++kd) {
+            hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, reinterpret_cast<unsigned *>(bh),
+                               (unsigned long long)(bar / 4));
+            int kdv = kd, it = (int)p0;
+            void *args[] = {&bh, &kdv, &it, &dirty, const_cast<unsigned long long *>(&dw),
+                            const_cast<unsigned long long *>(&limit)};
+            rc = timed([&] {
+                (void)hipLaunchCooperativeKernel((const void *)k_mb_barrier, dim3(G), dim3(BLOCK), args, 0, s);
+            });
+            if (rc) return rc;
+            int broken = 0;
+            HIP_TRY(hipMemcpy(&broken, &bh->broken, sizeof(int), hipMemcpyDeviceToHost), "barrier check");
+            if (broken) return fail(ctx, CSP_EDEVICE, "barrier microbenchmark: wrong combine or timeout");
+            r[kd] = 1000.0 * ms / (double)p0;
+        }
+    } else {
+        return fail(ctx, CSP_EINVAL, "unknown microbenchmark");
+    }
+    return CSP_OK;
 }
 
 int csp_set_pool_hint(csp_ctx *ctx, uint64_t flows_per_bucket)
