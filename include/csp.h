@@ -349,9 +349,15 @@ int csp_microbench(csp_ctx *ctx, int kind, int64_t p0, int64_t p1, int64_t p2, d
  * them from their own stream).
  *
  * Progress is made inside csp_serve_submit and csp_serve_poll; call poll
- * regularly.  When the server has nothing to do the workers leave, so the
- * GPU is free for other kernels; the next admitted request starts them
- * again.  One host thread uses a server at a time. */
+ * regularly.  The workers are one cooperative launch, so all of them are
+ * resident before any takes work (a request's gang of workers waits for
+ * its members at a barrier).  When the server has nothing to do the workers
+ * leave, so the GPU is free for other kernels; the next admitted request
+ * starts them again, and their launch waits for the CUs other kernels hold.
+ * If the host stops polling for 2 s the workers leave once every published
+ * slot has been taken.  A request whose gang barrier timed out completes
+ * with CSP_EDEVICE and its job slot is cleared for reuse.  One host thread
+ * uses a server at a time. */
 typedef struct csp_server csp_server;
 
 typedef struct {

@@ -2131,7 +2131,8 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Serving: one persistent launch that keeps taking solves while it runs.
+// Serving: one persistent, cooperative launch (every worker resident) that
+// keeps taking solves while it runs.
 //
 // The host publishes jobs in host-coherent (fine-grained) memory: a job
 // table, a ring of (job, range) slots and a tail counter.  Workers (one
@@ -4457,6 +4458,7 @@ struct SrvDone {
 struct csp_server {
     csp_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;          // clears a broken job's barrier while the workers run
     hipEvent_t ev_done = nullptr;
     bool running = false;
     bool stop_sent = false;
@@ -4536,8 +4538,12 @@ int srv_ensure_running(csp_server *s)
     a.watch = reinterpret_cast<unsigned *>(s->fixed + s->off_watch);
     a.stale = ctx->wall_khz * 2000ull;   // 2 s without a heartbeat
     a.max_jobs = (unsigned)s->max_jobs;
-    hipLaunchKernelGGL(k_serve, dim3(s->workers), dim3(BLOCK), s->lds, s->stream, a);
-    HIP_TRY(hipGetLastError(), "serving launch");
+    // cooperative: every worker is resident before any runs, so a gang of
+    // workers waiting for each other at its barrier is never left short
+    void *args[] = {&a};
+    HIP_TRY(hipLaunchCooperativeKernel((const void *)k_serve, dim3(s->workers), dim3(BLOCK), args, (unsigned)s->lds,
+                                       s->stream),
+            "serving launch");
     HIP_TRY(hipEventRecord(s->ev_done, s->stream), "event");
     s->running = true;
     return CSP_OK;
@@ -4694,8 +4700,19 @@ void srv_reap(csp_server *s)
         }
         d.c.path_len = (int64_t)d.path.size();
         s->path_alloc.give(a.path_off, a.path_len);
-        // a gang whose barrier broke leaves its barrier lines dirty: retire the job slot
-        if (st != ST_BROKEN) s->free_jobs.push_back(j);
+        // a gang whose barrier broke leaves its barrier lines dirty (and the
+        // broken flag set): every member has left the job, so clear them on
+        // the side stream before the slot is used again; retire the slot
+        // only if that fails
+        bool reuse = true;
+        if (st == ST_BROKEN) {
+            unsigned *bw = reinterpret_cast<unsigned *>(s->fixed + s->off_bar + (size_t)j * s->bar_stride);
+            const unsigned long long words = s->bar_stride / 4;
+            hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<unsigned long long>((words + 255) / 256, 1024ull)),
+                               dim3(256), 0, s->aux, bw, words);
+            reuse = hipGetLastError() == hipSuccess && hipStreamSynchronize(s->aux) == hipSuccess;
+        }
+        if (reuse) s->free_jobs.push_back(j);
         s->ready.push_back(std::move(d));
     }
     // overflowed requests go back to the front, in their original order
@@ -4721,6 +4738,8 @@ int csp_serve_open(csp_ctx *ctx, uint64_t arena_bytes, int max_jobs, csp_server 
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(CSP_EDEVICE, "serve stream", e);
+    if ((e = hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking)) != hipSuccess)
+        return bail(CSP_EDEVICE, "serve side stream", e);
     if ((e = hipEventCreateWithFlags(&s->ev_done, hipEventDisableTiming)) != hipSuccess)
         return bail(CSP_EDEVICE, "serve event", e);
     const void *kf = (const void *)k_serve;
@@ -4867,6 +4886,7 @@ int csp_serve_close(csp_server *s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->ev_done) (void)hipEventDestroy(s->ev_done);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->arena) (void)hipFree(s->arena);
     if (s->fixed) (void)hipFree(s->fixed);
     if (s->hctl) (void)hipHostFree(s->hctl);
