@@ -1521,18 +1521,27 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     };
 
     // Dense form of I_t (Step 8's condensed list in vertex order): sweep the
-    // frontier bitmap, two words per thread, into the list in ascending
-    // local index, so that the departure's lanes read the edge records of
-    // neighbouring vertices together.  The bitmap is left as it is (the
-    // departure clears it).
+    // frontier bitmap, two words per thread, into the list; each wave packs
+    // the set bits of its words in ascending local index at an offset taken
+    // from a shared counter (s_sw, zero on entry), so that the departure's
+    // lanes read the edge records of neighbouring vertices together.  The
+    // bitmap is left as it is (the departure clears it).
+    __shared__ unsigned s_sw;
     auto sweep = [=]() -> unsigned {
-        unsigned total = 0;
         for (unsigned w0 = 0; w0 < cw; w0 += 2 * BLOCK) {
             const unsigned wi = w0 + 2 * tid;
             const unsigned b0 = wi < cw ? fb[wi] : 0u, b1 = wi + 1 < cw ? fb[wi + 1] : 0u;
-            unsigned tot;
-            const unsigned ex = block_scan((unsigned)(__popc(b0) + __popc(b1)), s_wave, &tot);
-            unsigned k = total + ex;
+            const unsigned nb = (unsigned)(__popc(b0) + __popc(b1));
+            unsigned x = nb;                        // inclusive scan over the wave
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned y = __shfl_up(x, o);
+                if (lane >= (unsigned)o) x += y;
+            }
+            const unsigned wtot = __shfl(x, 63);
+            unsigned wbase = 0;
+            if (lane == 0 && wtot) wbase = atomicAdd(&s_sw, wtot);
+            unsigned k = __shfl(wbase, 0) + x - nb;
             unsigned bits = b0;
             while (bits) {
                 const unsigned bt = (unsigned)(__ffs(bits) - 1);
@@ -1545,10 +1554,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 bits &= bits - 1u;
                 list_put(k++, (wi + 1) * 32u + bt);
             }
-            total += tot;
         }
         __syncthreads();
-        return total;
+        return s_sw;
     };
 
     unsigned nlist = compact();
@@ -1918,6 +1926,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         if (tid == 0) {
             s_sum = 0;
             s_nl = 0;
+            s_sw = 0;
             s_bhn = 0;
             // atomic: other threads may still be flagging an overflow of the
             // candidate phase, and a lost flag would drop flows silently
