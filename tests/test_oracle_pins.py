@@ -391,3 +391,63 @@ def test_torch_generator_matches_numpy():
         assert np.array_equal(a1, b1.numpy()) and np.array_equal(a2, b2.numpy())
         for ax in range(d):
             assert np.array_equal(gen.face_mask(d, n, ax, 0), gen.face_mask_torch(d, n, ax, 0, "cpu").numpy())
+
+
+def _golden_recs(name):
+    return json.load(open(os.path.join(GOLDEN, name + ".json")))["problems"]
+
+
+def _batch_sample():
+    """Problems of the stored 1,024-problem batch the recurrence runs in
+    seconds: the four cheapest 2-D and 3-D ones and four near N T = 10^7."""
+    recs = _golden_recs("batch1024_s41")
+    cost = sorted(((g["n"] ** g["d"]) * max(g["T"], 1), g["j"]) for g in recs)
+    two = [j for c, j in cost if recs[j]["d"] == 2][:4]
+    three = [j for c, j in cost if recs[j]["d"] == 3][:4]
+    mid = [j for c, j in cost if 8e6 <= c <= 1.2e7][:4]
+    return sorted(set(two + three + mid))
+
+
+@pytest.mark.parametrize("j", _batch_sample())
+def test_batch1024_golden_sample_vs_recurrence(j):
+    """Stored oracle outputs of the batch (written by the oracle alone)
+    against the recurrence: T, X, x, Y, F2, every counter and the labels'
+    SHA-256, on a sample spanning d, n and K."""
+    import hashlib
+    g = _golden_recs("batch1024_s41")[j]
+    inst = gen.mixed_instance(41, j)
+    assert (inst.d, inst.n, inst.M) == (g["d"], g["n"], g["M"])
+    edges = pins.lattice_edge_list(inst.d, inst.n, inst.f1, inst.f2)
+    ref = pins.dp_solve(inst.N, edges, inst.A, inst.B, inst.M)
+    assert (ref["T"], ref["X"], ref["x"], ref["Y"], ref["F2"]) == (g["T"], g["X"], g["x"], g["Y"], g["F2"])
+    assert ref["counters"] == g["counters"]
+    assert hashlib.sha256(ref["labels"].astype("<u4").tobytes()).hexdigest() == g["labels_sha256"]
+
+
+@pytest.mark.parametrize("k", [4, 6, 7])
+def test_serve8_golden_vs_recurrence_and_path(k):
+    """Stored serving requests (the small ones): the first solve against the
+    recurrence, and the stored path is a lattice path from A to X whose
+    edges sum to (T, F2), re-solving one edge earlier each step."""
+    import hashlib
+    g = _golden_recs("serve8_s51")[k]
+    inst = gen.mixed_instance(51, k, (64, 1024), (32, 256))
+    edges = pins.lattice_edge_list(inst.d, inst.n, inst.f1, inst.f2)
+    ref = pins.dp_solve(inst.N, edges, inst.A, inst.B, inst.M)
+    assert (ref["T"], ref["X"], ref["x"], ref["Y"], ref["F2"]) == (g["T"], g["X"], g["x"], g["Y"], g["F2"])
+    assert ref["counters"] == g["counters"]
+    assert hashlib.sha256(ref["labels"].astype("<u4").tobytes()).hexdigest() == g["labels_sha256"]
+    path, rows = g["path"], g["resolves"]
+    assert g["path_complete"] and inst.A[path[0]] and path[-1] == g["X"] and len(set(path)) == len(path)
+    N, n, d = inst.N, inst.n, inst.d
+    s1 = s2 = 0
+    for u, v in zip(path[:-1], path[1:]):
+        lo, delta = min(u, v), abs(u - v)
+        ax = next(a for a in range(d) if n ** a == delta)
+        assert (lo // n ** ax) % n < n - 1
+        s1 += int(inst.f1[ax * N + lo])
+        s2 += int(inst.f2[ax * N + lo])
+    assert (s1, s2) == (g["T"], g["F2"])
+    # each re-solve ends one edge earlier on the path
+    assert [r[1] for r in rows] == path[::-1][:len(rows)]
+    assert [r[3] for r in rows] == path[::-1][1:len(rows) + 1]
