@@ -43,6 +43,12 @@ WORKLOADS = {
                           label_bytes=4),
     "square64": dict(desc="d=2 n=64, f1,f2 iid U{1..5} seed 1, columns x=0 -> x=63, M=200",
                      build=lambda gen: [gen.square64(1)], sample_index=0, label_bytes=2),
+    "env7": dict(desc="the environments of section 7 on [-1024,1024] x [0,2048] (2049^2 vertices, passage times "
+                      "in {1,2}, f2=f1, M above every path weight, water from the x-axis): Lemma 1's (the y-axis "
+                      "fast), Theorem 2's construction at t=1024, and the random one with p=1/2 (seed 71)",
+                 build=lambda gen: [gen.lemma1_environment(1024), gen.fractal_environment(10),
+                                    gen.binary_environment(1024, 0.5, 71)],
+                 sample_index=None, label_bytes=4),
     "paper_cubes": dict(desc="the paper's runs (section 8): d=3 cubes n=50,75,100,125, water on the cube "
                              "boundary, B the centre vertex, f1,f2 iid U{1..100} seed 61, M=10000",
                         build=lambda gen: [gen.cube_boundary_to_center(n, 61, K=100, M=10000)
@@ -496,6 +502,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="lattice workloads: autotune each lattice shape before timing (traffic reported "
                          "null); batch1024: autotune the gang size")
+    ap.add_argument("--dense-sweep", type=int, nargs="*", default=None,
+                    help="lattice workloads: also time each solve with these dense thresholds of the improved "
+                         "set (-1 never), untimed by the step")
     ap.add_argument("--trace", action="store_true",
                     help="also report |I_t| and water in transit against t (one extra solve each, untimed)")
     args = ap.parse_args()
@@ -599,6 +608,21 @@ def main():
         line["autotune"] = tuned
     if args.trace:
         line["trace"] = [trace_summary(csp, solver, torch, di) for di in dev]
+    if args.dense_sweep is not None:
+        sweep = []
+        for thr in args.dense_sweep:
+            csp.csp_set_dense_threshold(solver.ctx, (1 << 32) - 1 if thr < 0 else thr)
+            ms = []
+            for di in dev:
+                solver.solve(di, stream=stream)
+                reps = []
+                for _ in range(3):
+                    solver.solve(di, stream=stream)
+                    reps.append(csp.csp_last_kernel_ms(solver.ctx))
+                ms.append(round(min(reps), 3))
+            sweep.append({"dense_threshold": thr, "kernel_ms": ms})
+        csp.csp_set_dense_threshold(solver.ctx, -1)
+        line["dense_sweep"] = sweep
     if not args.no_cpu_baseline and wl["sample_index"] is not None:
         line["cpu_baseline"] = cpu_baseline(args.workload, insts[wl["sample_index"]])
     print(json.dumps(line), flush=True)
