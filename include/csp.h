@@ -267,10 +267,10 @@ int csp_autotune_clear(csp_ctx *ctx);
  * form), so that neighbouring vertices' edge records are read together in
  * the sending step.  0 sweeps every cycle; a value of 2^32 - 1 or more
  * never sweeps; -1 (the default) restores the automatic choice (the
- * autotuned value for the lattice shape, else the library's default).
+ * autotuned value for the lattice shape, else 4096).
  * Changes speed, never results.  csp_autotune tries, on the configuration
- * it chose, the thresholds never, 0, 256, 1024 and 4096 and records the
- * fastest (when at least 3 % faster than the automatic one);
+ * it chose, the thresholds never, 0, 1024, 2048, 4096 and 8192 and records
+ * the fastest (when at least 3 % faster than the automatic one);
  * csp_tuned_dense_threshold reports what it recorded for a shape (-1:
  * nothing, the automatic choice applies). */
 int csp_set_dense_threshold(csp_ctx *ctx, int64_t vertices);
