@@ -502,6 +502,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="lattice workloads: autotune each lattice shape before timing (traffic reported "
                          "null); batch1024: autotune the gang size")
+    ap.add_argument("--path", type=int, default=0,
+                    help="lattice workloads: 0 automatic, 1 contiguous ranges, 2 global labels, 3 x-pencil ranges (d=3)")
     ap.add_argument("--dense-sweep", type=int, nargs="*", default=None,
                     help="lattice workloads: also time each solve with these dense thresholds of the improved "
                          "set (-1 never), untimed by the step")
@@ -538,6 +540,8 @@ def main():
     dev = [csp.to_device(i) for i in insts]
     solver = csp.Solver(0)
     stream = torch.cuda.current_stream()
+    if args.path:
+        csp.csp_set_path(solver.ctx, args.path)
 
     tuned = []
     if args.autotune:

@@ -236,8 +236,11 @@ int csp_set_blocks(csp_ctx *ctx, int blocks);
  * (each workgroup keeps a range of consecutive vertex indices, with their
  * labels in LDS; CSP_EINVAL when a range cannot fit), 2 = global labels,
  * 3 = range-owned with x-pencil ranges for d = 3 (n x t x t vertices; other
- * d as 1).  Changes speed, never results.  csp_last_path returns the kernel
- * (1 range-owned, 2 global labels) the last solve used. */
+ * d as 1).  Automatic: the autotuned choice for the lattice shape, else
+ * x-pencils for 3-d lattices of 2^23 vertices or more, else range-owned
+ * when a range fits in LDS, else global labels.  Changes speed, never
+ * results.  csp_last_path returns the kernel (1 range-owned, 2 global
+ * labels) the last solve used. */
 int csp_set_path(csp_ctx *ctx, int path);
 int csp_last_path(const csp_ctx *ctx);
 

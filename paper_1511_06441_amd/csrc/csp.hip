@@ -3150,11 +3150,19 @@ const csp_ctx::Tuned *tuned_for(const csp_ctx *ctx, int d, long long N)
 }
 
 // Kernel choice of a solve: the override, else the autotuned one, else automatic.
+// Kernel path of a solve: the override, else the autotuned one, else
+// x-pencil ranges for 3-d lattices of 2^23 vertices or more and the
+// automatic choice below that.  Pencils ship candidates only across their
+// y and z faces (a quarter or less of the cross-range tests of whole-plane
+// ranges); measured on MI355X they win on the 256^3 cubes (sparse 307.3 ->
+// 286.6 ms, stress 9.42 -> 8.82 ms) and lose on the 128^3 cubes (+3 %) and
+// the paper's 50^3..125^3 cubes (+7 %), whose ranges are smaller.
 int path_for(const csp_ctx *ctx, int d, long long N)
 {
     if (ctx->path_override) return ctx->path_override;
     const csp_ctx::Tuned *e = tuned_for(ctx, d, N);
-    return e ? e->path : 0;
+    if (e) return e->path;
+    return d == 3 && N >= (1ll << 23) ? 3 : 0;
 }
 
 int blocks_for(csp_ctx *ctx, int d, long long N)
