@@ -247,7 +247,8 @@ int csp_last_path(const csp_ctx *ctx);
 /* Autotuning of the single-solve kernel for one lattice shape.  Solves the
  * problem (arguments as csp_solve_dev) twice per candidate configuration:
  * workgroup counts of 1/4, 1/2, 1 and 2 times the automatic choice, and for
- * d = 3 both range shapes (csp_set_path 0 and 3).  Every configuration must
+ * d = 3 both range shapes and the global-label kernel (csp_set_path 1, 3
+ * and 2).  Every configuration must
  * give the same result and counters (else CSP_EDEVICE).  The fastest, by
  * kernel time (the automatic configuration unless another is at least 3 %
  * faster), is recorded on ctx and used by later csp_solve_dev,

@@ -3161,7 +3161,7 @@ int path_for(const csp_ctx *ctx, int d, long long N)
 {
     if (ctx->path_override) return ctx->path_override;
     const csp_ctx::Tuned *e = tuned_for(ctx, d, N);
-    if (e) return e->path;
+    if (e && e->path) return e->path;              // 0 recorded: the automatic choice won
     return d == 3 && N >= (1ll << 23) ? 3 : 0;
 }
 
@@ -4972,13 +4972,19 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
     ctx->blocks_override = 0;
     ctx->path_override = 0;
     // candidates: workgroup counts around the automatic choice; for d = 3
-    // also x-pencil ranges (path 0 is the automatic kernel choice)
+    // both range shapes explicitly (contiguous ranges, path 1, and x-pencils,
+    // path 3), whichever the automatic choice would be, and the global-label
+    // kernel; else path 0 (the automatic kernel choice)
     const int b0 = blocks_for(ctx, d, N);
     std::vector<int> bs;
     for (int b : {b0, b0 / 2, b0 / 4, 2 * b0})
         if (b >= 1 && b <= ctx->max_blocks[d] && std::find(bs.begin(), bs.end(), b) == bs.end()) bs.push_back(b);
     std::vector<int> ps = {0};
-    if (d == 3) ps.push_back(3);
+    if (d == 3) ps = {1, 3, 2};                   // 2 (global labels) always fits
+    // the configuration the automatic choice would run (path_for without a
+    // tuned entry): the baseline the 3 % rule compares with
+    const int auto_p = d == 3 ? (N >= (1ll << 23) ? 3 : 1) : 0;
+    bool have_base = false;
     csp_result r0, r1;
     csp_counters c0, c1;
     bool have = false;
@@ -4994,7 +5000,7 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
                 rc = solve_impl(ctx, d, n, f1, f2, A, B, M, nullptr, &r1, &c1, 0, stream, false);
                 if (rc == CSP_OK && (t < 0.f || ctx->last_ms < t)) t = ctx->last_ms;
             }
-            if (rc == CSP_EINVAL && pth == 3) {         // pencils do not fit: not a candidate
+            if (rc == CSP_EINVAL && pth != 0) {         // this range shape does not fit: not a candidate
                 rc = CSP_OK;
                 continue;
             }
@@ -5004,11 +5010,14 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
                 ctx->dense_override = save_dense;
                 return rc;
             }
+            if (!have_base && (!have || (pth == auto_p && b == b0))) {
+                base = csp_ctx::Tuned{d, N, b, pth, t, -1};  // the automatic configuration
+                have_base = pth == auto_p && b == b0;
+            }
             if (!have) {
                 r0 = r1;
                 c0 = c1;
                 have = true;
-                base = csp_ctx::Tuned{d, N, b, pth, t, -1};  // the automatic configuration
             } else if (memcmp(&r0, &r1, sizeof(r0)) != 0 || memcmp(&c0, &c1, sizeof(c0)) != 0) {
                 ctx->blocks_override = save_b;
                 ctx->path_override = save_p;
