@@ -736,15 +736,17 @@ __global__ void __launch_bounds__(BLOCK) k_solve(Params p)
 //
 // A neighbour test across ranges is shipped instead: the sender writes a
 // candidate (vertex, quality, f1, direction) to the neighbouring range, and
-// that range's owner runs the test against its own labels at the start of
-// the next cycle, before any later delivery can change them, filing the flow
-// itself if it passes.  All flows into a range therefore sit in that range's
-// own wheel (per-bucket fills in LDS), and a cycle needs one grid barrier:
+// that range's owner runs the test against its own labels before its next
+// delivery can change them, filing the flow itself if it passes.  All flows
+// into a range therefore sit in that range's own wheel (per-bucket fills in
+// LDS), and a cycle needs one grid barrier:
 //
-//   accept candidates sent at t_prev (Steps 4-5 across ranges)
-//   deliver bucket t, commit labels, build I_t (Steps 1-3, 8)
 //   send from I_t inside the range, ship candidates out (Steps 4-5)
-//   barrier, combining the next event time, flags, counts and the best B key
+//   arrive at the barrier; once the neighbouring ranges have arrived, accept
+//     the candidates they shipped at t (Steps 4-5 across ranges)
+//   barrier release, combining the next event time, flags, counts and the
+//     best B key
+//   deliver the next bucket, commit labels, build I_t (Steps 1-3, 8)
 //
 // The barrier's result decides termination (Steps 6 and 1) identically in
 // every workgroup; the departure of the terminal cycle is discarded.
@@ -1018,11 +1020,15 @@ __device__ __forceinline__ void gang_or_sums(BarHdr *bh, unsigned g, unsigned e,
     s2 = v[2];
 }
 
-__device__ bool gang_or(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
-                        const Comb &mine, Comb &out, unsigned long long *tpub = nullptr)
+// First half of gang_or: member m arrives at barrier epoch + 1 (epoch is
+// advanced).  Before its arrival it stores the new epoch in word 12 of its
+// slot line, after every access of the workgroup has completed: a range
+// that reads this member's candidates may do so once it sees that word,
+// without waiting for the whole gang.  The member that completes the root
+// releases everyone here.
+__device__ void gang_or_arrive(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, const Comb &mine,
+                               unsigned long long *tpub = nullptr)
 {
-    __shared__ int s_ok;
-    __shared__ unsigned long long s_o[2];
     const unsigned e = epoch + 1;
     if (g > 1 && threadIdx.x == 0) {
         if (mine.mn != 0xFFFFFFFFu && mine.mn > OR_ND)
@@ -1031,80 +1037,108 @@ __device__ bool gang_or(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, uns
     vm_drain();
     __syncthreads();
     epoch = e;
+    if (g == 1 || threadIdx.x >= 64) return;
+    const unsigned lane = threadIdx.x;
+    const unsigned MG = or_group_size(g);                      // members per group
+    const unsigned ngr = (g + MG - 1) / MG;
+    const unsigned grp = m / MG, gsz = min(MG, g - grp * MG);
+    const unsigned long long tag = (unsigned long long)e << 32;
+    if (tpub && lane == 0) *tpub = wall_clock64();
+    unsigned long long comb = 0, rel = 2;  // rel: 2 not the releaser, 1 releaser reading far deltas, 0 releaser
+    if (lane == 0) {
+        st64(&bar_slot(bh, m)[12], (unsigned long long)e);
+        unsigned long long w = (1ull << (m - grp * MG)) | ((unsigned long long)(mine.orf >> 28) << 32);
+        if (mine.mn != 0xFFFFFFFFu) w |= mine.mn <= OR_ND ? 1ull << (OR_D0 + mine.mn - 1) : 1ull << OR_FAR;
+        unsigned long long *gw = &bh->ow[e & 1][grp][0];
+        const unsigned long long full_g = gsz == 64 ? ~0ull : (1ull << gsz) - 1;
+        const unsigned long long og = __hip_atomic_fetch_or(gw, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | w;
+        if ((og & 0xFFFFFFFFull) == full_g) {
+            // last of its group: forward the group to the root
+            const unsigned long long rw = (og & ~0xFFFFFFFFull) | (1ull << grp);
+            const unsigned long long full_r = (1ull << ngr) - 1;
+            const unsigned long long orr =
+                __hip_atomic_fetch_or(&bh->oroot[e & 1][0], rw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | rw;
+            if ((orr & 0xFFFFFFFFull) == full_r) {
+                // last group: combine and release.  The arrival words of
+                // this parity are cleared for the barrier after next.
+                for (unsigned k = 0; k < ngr; ++k) st64(&bh->ow[e & 1][k][0], 0ull);
+                st64(&bh->oroot[e & 1][0], 0ull);
+                const unsigned long long near = (orr >> OR_D0) & ((1ull << OR_ND) - 1);
+                unsigned mn = 0xFFFFFFFFu;
+                if (near) mn = (unsigned)__builtin_ctzll(near) + 1;
+                rel = ((orr >> OR_FAR) & 1ull) && !near ? 1 : 0;
+                comb = ((unsigned long long)((orr >> 32) & 0xFull) << 32) | mn;
+            }
+        }
+    }
+    // the releaser reads the far deltas when there is no near one
+    rel = __shfl(rel, 0);
+    if (rel != 2) {
+        comb = __shfl(comb, 0);
+        unsigned mn = (unsigned)comb, orf4 = (unsigned)(comb >> 32);
+        if (rel == 1) {
+            unsigned fm = 0xFFFFFFFFu;
+            for (unsigned i = lane; i < g; i += 64) {
+                const unsigned long long v = ld64(&bar_slot(bh, i)[8]);
+                if ((v & 0xFFFFFFFF00000000ull) == tag) fm = min(fm, (unsigned)v);
+            }
+            for (int o = 32; o > 0; o >>= 1) fm = min(fm, (unsigned)__shfl_xor(fm, o));
+            mn = fm;
+        }
+        const unsigned long long rw = tag | ((unsigned long long)orf4 << 16) | (mn < 0xFFFFu ? mn : 0xFFFFu);
+        for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], rw);
+    }
+}
+
+// Wait until member m of a gang whose members announce their arrival with
+// gang_or_arrive has arrived at barrier e (word 12 of its slot line); false
+// after `limit` ticks or when the gang is broken.  One lane calls it.
+__device__ bool gang_or_seen(BarHdr *bh, unsigned m, unsigned e, unsigned long long limit)
+{
+    const unsigned long long *w = &bar_slot(bh, m)[12];
+    if (ld64(w) >= (unsigned long long)e) return true;
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        if (ld64(w) >= (unsigned long long)e) return true;
+        if (wall_clock64() - t0 > limit) {
+            __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    }
+}
+
+// Second half of gang_or: wait for the release of barrier epoch (the one
+// gang_or_arrive entered) and return its flags, least delta and B key.
+__device__ bool gang_or_wait(BarHdr *bh, unsigned g, unsigned m, unsigned epoch, unsigned long long limit,
+                             const Comb &mine, Comb &out)
+{
+    __shared__ int s_ok;
+    __shared__ unsigned long long s_o[2];
     if (g == 1) {
         out = mine;
         out.rest = nullptr;
         return true;
     }
-    if (threadIdx.x < 64) {
-        const unsigned lane = threadIdx.x;
-        const unsigned MG = or_group_size(g);                  // members per group
-        const unsigned ngr = (g + MG - 1) / MG;
-        const unsigned grp = m / MG, gsz = min(MG, g - grp * MG);
-        const unsigned long long tag = (unsigned long long)e << 32;
+    if (threadIdx.x == 0) {
         int ok = 1;
         const unsigned long long t0 = wall_clock64();
-        if (tpub && lane == 0) *tpub = t0;
-        unsigned long long comb = 0, rel = 2;  // rel: 2 not the releaser, 1 releaser reading far deltas, 0 releaser
-        if (lane == 0) {
-            unsigned long long w = (1ull << (m - grp * MG)) | ((unsigned long long)(mine.orf >> 28) << 32);
-            if (mine.mn != 0xFFFFFFFFu) w |= mine.mn <= OR_ND ? 1ull << (OR_D0 + mine.mn - 1) : 1ull << OR_FAR;
-            unsigned long long *gw = &bh->ow[e & 1][grp][0];
-            const unsigned long long full_g = gsz == 64 ? ~0ull : (1ull << gsz) - 1;
-            const unsigned long long og = __hip_atomic_fetch_or(gw, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | w;
-            if ((og & 0xFFFFFFFFull) == full_g) {
-                // last of its group: forward the group to the root
-                const unsigned long long rw = (og & ~0xFFFFFFFFull) | (1ull << grp);
-                const unsigned long long full_r = (1ull << ngr) - 1;
-                const unsigned long long orr =
-                    __hip_atomic_fetch_or(&bh->oroot[e & 1][0], rw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | rw;
-                if ((orr & 0xFFFFFFFFull) == full_r) {
-                    // last group: combine and release.  The arrival words of
-                    // this parity are cleared for the barrier after next.
-                    for (unsigned k = 0; k < ngr; ++k) st64(&bh->ow[e & 1][k][0], 0ull);
-                    st64(&bh->oroot[e & 1][0], 0ull);
-                    const unsigned long long near = (orr >> OR_D0) & ((1ull << OR_ND) - 1);
-                    unsigned mn = 0xFFFFFFFFu;
-                    if (near) mn = (unsigned)__builtin_ctzll(near) + 1;
-                    rel = ((orr >> OR_FAR) & 1ull) && !near ? 1 : 0;
-                    comb = ((unsigned long long)((orr >> 32) & 0xFull) << 32) | mn;
-                }
+        unsigned long long *fl = bar_flag(bh, g, m);
+        unsigned long long w;
+        while (((w = ld64(&fl[0])) >> 32) < (unsigned long long)epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wall_clock64() - t0 > limit) {
+                __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
             }
         }
-        // the releaser reads the far deltas when there is no near one
-        rel = __shfl(rel, 0);
-        if (rel != 2) {
-            comb = __shfl(comb, 0);
-            unsigned mn = (unsigned)comb, orf4 = (unsigned)(comb >> 32);
-            if (rel == 1) {
-                unsigned fm = 0xFFFFFFFFu;
-                for (unsigned i = lane; i < g; i += 64) {
-                    const unsigned long long v = ld64(&bar_slot(bh, i)[8]);
-                    if ((v & 0xFFFFFFFF00000000ull) == tag) fm = min(fm, (unsigned)v);
-                }
-                for (int o = 32; o > 0; o >>= 1) fm = min(fm, (unsigned)__shfl_xor(fm, o));
-                mn = fm;
-            }
-            const unsigned long long rw = tag | ((unsigned long long)orf4 << 16) | (mn < 0xFFFFu ? mn : 0xFFFFu);
-            for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], rw);
-        }
-        if (lane == 0) {
-            unsigned long long *fl = bar_flag(bh, g, m);
-            unsigned long long w;
-            while (((w = ld64(&fl[0])) >> 32) < (unsigned long long)e) {
-                __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > limit) {
-                    __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-            }
-            if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-            const unsigned mn16 = (unsigned)(w & 0xFFFFu), orf = (unsigned)((w >> 16) & 0xFu) << 28;
-            s_o[0] = (unsigned long long)(mn16 == 0xFFFFu ? 0xFFFFFFFFu : mn16) | ((unsigned long long)orf << 32);
-            s_o[1] = (orf & SF_BHIT) ? ld64(&bh->bkey[0]) : 0;
-            s_ok = ok;
-        }
+        if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        const unsigned mn16 = (unsigned)(w & 0xFFFFu), orf = (unsigned)((w >> 16) & 0xFu) << 28;
+        s_o[0] = (unsigned long long)(mn16 == 0xFFFFu ? 0xFFFFFFFFu : mn16) | ((unsigned long long)orf << 32);
+        s_o[1] = (orf & SF_BHIT) ? ld64(&bh->bkey[0]) : 0;
+        s_ok = ok;
     }
     __syncthreads();
     out.mn = (unsigned)s_o[0];
@@ -1115,6 +1149,13 @@ __device__ bool gang_or(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, uns
     const bool ok = s_ok != 0;
     __syncthreads();
     return ok;
+}
+
+__device__ bool gang_or(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, unsigned long long limit,
+                        const Comb &mine, Comb &out, unsigned long long *tpub = nullptr)
+{
+    gang_or_arrive(bh, g, m, epoch, mine, tpub);
+    return gang_or_wait(bh, g, m, epoch, limit, mine, out);
 }
 
 // Offset of the neighbour in direction dir (0..D-1: -stride[D-1..0],
@@ -1241,9 +1282,10 @@ constexpr unsigned SF_BAD = 1u << 28;      // an edge with f1 or f2 equal to 0
 // Then each cycle:
 //   departure (Steps 4-5) from I_t: inside the range, test and file flows;
 //     across ranges, ship candidates to the owning range
-//   barrier: next event time, flags, counts, best B key (Steps 1, 6)
-//   accept candidates shipped at t_prev against this range's labels
-//   arrival (Steps 1-3, 8): deliver bucket t, commit labels, build I_t
+//   barrier arrival; once the neighbouring ranges have arrived, accept the
+//     candidates they shipped at t against this range's labels
+//   barrier release: next event time, flags, counts, best B key (Steps 1, 6)
+//   arrival (Steps 1-3, 8): deliver the next bucket, commit labels, build I_t
 // What every member of the gang knows when a solve ends; yd (direction of
 // the last edge seen from X) is known only to X's owner.
 struct RunRes {
@@ -1276,6 +1318,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     __shared__ unsigned long long s_red[4];
     __shared__ unsigned s_ccnt[NOMAX];        // candidates shipped / received this cycle
     __shared__ unsigned s_nl, s_bhn;          // size of I_t; improved vertices of B
+    __shared__ unsigned s_nbad;               // a neighbour never arrived (gang broken)
     __shared__ unsigned s_cpre[NOMAX + 1];
 
     const unsigned tid = threadIdx.x, lane = lane_id();
@@ -1359,7 +1402,6 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0}, ph_t = 0;
     // phase timing 1: range 0 only; 2: every range (sums and maxima)
     const bool timing = tid == 0 && (p.prof == 2 || (p.prof && lead));
-    __shared__ unsigned long long s_tpub;
 #define PHASE4(k)                                            \
     do {                                                     \
         if (timing) {                                        \
@@ -1631,7 +1673,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     unsigned *wptr = LOG ? p.wptr + (unsigned long long)r * W * S : nullptr;
 
     rr.X = rr.LX = 0;
-    long long t = 0, t_prev = 0;
+    long long t = 0;
     unsigned cyc = 0, par = 0;
     unsigned F = 0;                     // flows delivered this cycle
     unsigned long long transit = 0;     // flows in transit after the previous sending round
@@ -1771,17 +1813,82 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         mine.s1 = nlist;
         mine.s2 = transit;
         mine.mx = s_xkey;
-        if (!gang_or(p.bar, G, r, epoch, p.wait_limit, mine, all, p.prof ? &s_tpub : nullptr)) {
+        if (tid == 0) s_nbad = 0;
+        gang_or_arrive(p.bar, G, r, epoch, mine);
+        PHASE4(1);
+        // ---- Steps 4-5 across ranges: test the candidates the neighbours
+        // shipped at t against this range's labels (still L_t) and file the
+        // flows, while the barrier completes: a neighbour's candidates are
+        // complete once it has arrived.  A run that ends at this barrier
+        // (T found, overflow) discards what is filed here; it is counted
+        // (cEx) only when the run goes on.
+        unsigned long long cEx = 0;
+        if (tid >= 64 && tid - 64 < (unsigned)NO) {      // wave 1: wave 0 is arriving
+            const unsigned sl = tid - 64;
+            const long long so = soff((int)sl);           // slot sl comes from range r - so
+            const long long src = (long long)r - so;
+            unsigned v = 0;
+            if (so != 0 && src >= 0 && src < (long long)G) {
+                if (gang_or_seen(p.bar, (unsigned)src, epoch, p.wait_limit))
+                    v = __hip_atomic_load(pubc(par, (unsigned long long)src, sl), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    s_nbad = 1;
+            }
+            s_ccnt[sl] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_cpre[0] = 0;
+            for (int oi = 0; oi < NO; ++oi) s_cpre[oi + 1] = s_cpre[oi] + s_ccnt[oi];
+        }
+        __syncthreads();
+        {
+            const unsigned FC = s_cpre[NO];
+            constexpr int UC = 4;                   // candidate loads in flight per thread
+            for (unsigned j0 = tid; j0 < FC; j0 += BLOCK * UC) {
+              uint2 cdu[UC];
+              unsigned cpu[UC];
+#pragma unroll
+              for (int u = 0; u < UC; ++u) {
+                const unsigned j = j0 + u * BLOCK;
+                if (j < FC) {
+                    int oi = 0;
+                    while (j >= s_cpre[oi + 1]) ++oi;
+                    const long long src = (long long)r - soff(oi);
+                    const uint2 *cb = candbuf(par, (unsigned long long)src, (unsigned)oi);
+                    cdu[u] = cand_get(cb + (j - s_cpre[oi]));
+                    if constexpr (LOG)
+                        cpu[u] = __hip_atomic_load(&p.cptr[(cb - cand) + (j - s_cpre[oi])], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < UC; ++u) {
+                if (j0 + u * BLOCK >= FC) continue;
+                const uint2 cd = cdu[u];
+                const unsigned li = cd.x & CAND_LI, a1 = (cd.x >> 17) & 0xFFu, rdir = cd.x >> 25;
+                if (cd.y > lget(lab, l16, li)) {
+                    const unsigned bk = (unsigned)((t + a1) & Wm);
+                    const unsigned pos = atomicAdd(&cnt[bk], 1u);
+                    if (pos < S) {
+                        wheel[(unsigned long long)bk * S + pos] = make_uint2((unsigned)(base + li), (cd.y << 3) | rdir);
+                        if constexpr (LOG) wptr[(unsigned long long)bk * S + pos] = cpu[u];
+                    } else {
+                        atomicOr(&s_flags, SF_OVER);
+                    }
+                    ++cEx;
+                }
+              }
+            }
+        }
+        par ^= 1u;
+        PHASE4(2);
+        if (!gang_or_wait(p.bar, G, r, epoch, p.wait_limit, mine, all) || s_nbad) {
             status = ST_BROKEN;
             break;
         }
-        if (timing) {
-            // publish (release fence, counting, the combine when last) and wait
-            const unsigned long long now_ = wall_clock64();
-            ph[1] += s_tpub - ph_t;
-            ph[4] += now_ - s_tpub;
-            ph_t = now_;
-        }
+        PHASE4(4);
 
         // the counters' sums are needed by the lead only; it clears the
         // ring line they came in for a later barrier
@@ -1859,70 +1966,12 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             break;
         }
         cD += dD;
-        cE += dE;
+        cE += dE + cEx;
         if (all.mn == 0xFFFFFFFFu) { status = ST_DONE; break; }          // condition 2
         if (p.max_cycles > 0 && (long long)cyc >= p.max_cycles) { status = ST_CANCELED; break; }
-        t_prev = t;
         t += all.mn;
         ++cyc;
 
-        // ---- Steps 4-5 across ranges: test candidates shipped at t_prev
-        // against this range's labels (still L_{t_prev}) and file the flows.
-        if (tid < (unsigned)NO) {
-            const long long so = soff((int)tid);         // slot tid comes from range r - so
-            const long long src = (long long)r - so;
-            unsigned v = 0;
-            if (so != 0 && src >= 0 && src < (long long)G)
-                v = __hip_atomic_load(pubc(par, (unsigned long long)src, tid), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-            s_ccnt[tid] = v;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            s_cpre[0] = 0;
-            for (int oi = 0; oi < NO; ++oi) s_cpre[oi + 1] = s_cpre[oi] + s_ccnt[oi];
-        }
-        __syncthreads();
-        {
-            const unsigned FC = s_cpre[NO];
-            constexpr int UC = 4;                   // candidate loads in flight per thread
-            for (unsigned j0 = tid; j0 < FC; j0 += BLOCK * UC) {
-              uint2 cdu[UC];
-              unsigned cpu[UC];
-#pragma unroll
-              for (int u = 0; u < UC; ++u) {
-                const unsigned j = j0 + u * BLOCK;
-                if (j < FC) {
-                    int oi = 0;
-                    while (j >= s_cpre[oi + 1]) ++oi;
-                    const long long src = (long long)r - soff(oi);
-                    const uint2 *cb = candbuf(par, (unsigned long long)src, (unsigned)oi);
-                    cdu[u] = cand_get(cb + (j - s_cpre[oi]));
-                    if constexpr (LOG)
-                        cpu[u] = __hip_atomic_load(&p.cptr[(cb - cand) + (j - s_cpre[oi])], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < UC; ++u) {
-                if (j0 + u * BLOCK >= FC) continue;
-                const uint2 cd = cdu[u];
-                const unsigned li = cd.x & CAND_LI, a1 = (cd.x >> 17) & 0xFFu, rdir = cd.x >> 25;
-                if (cd.y > lget(lab, l16, li)) {
-                    const unsigned bk = (unsigned)((t_prev + a1) & Wm);
-                    const unsigned pos = atomicAdd(&cnt[bk], 1u);
-                    if (pos < S) {
-                        wheel[(unsigned long long)bk * S + pos] = make_uint2((unsigned)(base + li), (cd.y << 3) | rdir);
-                        if constexpr (LOG) wptr[(unsigned long long)bk * S + pos] = cpu[u];
-                    } else {
-                        atomicOr(&s_flags, SF_OVER);
-                    }
-                    ++cE;
-                }
-              }
-            }
-        }
-        par ^= 1u;
         if (tid == 0) {
             s_sum = 0;
             s_nl = 0;
@@ -1934,8 +1983,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
             s_xkey = 0;
         }
         __syncthreads();
-        PHASE4(2);
-        // flows in transit after the sending round at t_prev
+        // flows in transit after the sending round of the previous time
         {
             unsigned long long tr = 0;
             for (unsigned bk = tid; bk < W; bk += BLOCK) tr += cnt[bk];
