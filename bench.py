@@ -356,6 +356,12 @@ def run_micro(args):
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     mb(csp.MB_COPY, 1 << 30, 1)
     out = {"copy_1GiB_GBps": mb(csp.MB_COPY, 1 << 30, 10)[0]}
+    # smaller copies: 2 x 8 MiB stays in the L2s (4 MiB per XCD), 2 x 64 MiB
+    # and 2 x 96 MiB in the 256 MiB Infinity Cache
+    out["copy_GBps_by_size"] = {}
+    for mib in (8, 64, 96, 256):
+        mb(csp.MB_COPY, mib << 20, 2)
+        out["copy_GBps_by_size"][f"{mib}MiB"] = mb(csp.MB_COPY, mib << 20, 200 if mib < 256 else 50)[0]
     mb(csp.MB_ATOMIC, 1 << 24, 1 << 24)
     out["atomicmax_scattered_Gps"] = {"64MiB": mb(csp.MB_ATOMIC, 1 << 28, 1 << 24)[0],
                                       "1GiB": mb(csp.MB_ATOMIC, 1 << 28, 1 << 28)[0]}
@@ -364,6 +370,13 @@ def run_micro(args):
         mb(csp.MB_LOADS, nr, 10)
         g, us = mb(csp.MB_LOADS, nr, 400)
         out["record_loads"][f"{nr}_per_cu"] = {"G_loads_per_s": g, "us_per_round": us}
+    # 3,400 loads per CU and round from slabs of 2^lg records per CU: 16 MiB
+    # in all (lg 12, in the L2s) up to 1 GiB (lg 18, beyond the Infinity Cache)
+    out["record_loads_by_footprint"] = {}
+    for lg in (12, 14, 15, 16, 18):
+        mb(csp.MB_LOADS, 3400, 10, lg)
+        g, us = mb(csp.MB_LOADS, 3400, 400, lg)
+        out["record_loads_by_footprint"][f"{(cus << lg) * 16 >> 20}MiB"] = {"G_loads_per_s": g, "us_per_round": us}
     out["barrier_us"] = {}
     for dirty in (0, 64, 256):
         mb(csp.MB_BARRIER, 100, cus, dirty)

@@ -306,10 +306,11 @@ int csp_last_phase_us(const csp_ctx *ctx, double *us);
  * csp_set_phase_timing(ctx, 2) each workgroup times its own phases, and
  * after a solve mean[6] and max[6] receive, per phase, the mean over the
  * workgroups and the largest single workgroup's total, in microseconds:
- * slot 0 the sending step (Steps 4-5 inside the range), 1 publishing at
- * the barrier (release fence, counting in, and the combine for the last
- * to arrive), 4 waiting for the barrier's release, 2 testing the
- * candidates other ranges shipped, 3 the deliveries (Steps 1-3, 8) and
+ * slot 0 the sending step (Steps 4-5 inside the range), 1 arriving at
+ * the barrier (completing the workgroup's accesses, counting in, and the
+ * release for the last to arrive), 2 waiting for the neighbouring ranges'
+ * arrival and testing the candidates they shipped (before the release),
+ * 4 waiting for the barrier's release, 3 the deliveries (Steps 1-3, 8) and
  * building I_t.  Zero when the last solve took the global-label kernel. */
 int csp_last_phase_spread(const csp_ctx *ctx, double *mean, double *max);
 
@@ -320,9 +321,9 @@ int csp_last_phase_spread(const csp_ctx *ctx, double *mean, double *max);
  *   kind 1: p0 32-bit atomic maxima at hashed positions of p1 words (a power
  *           of two); r[0] = G atomics/s.
  *   kind 2: one workgroup per CU, each doing p0 16-byte loads at hashed
- *           positions of its own 1 MiB slab per round, p1 rounds (the edge
- *           record fetches of the sending step); r[0] = G loads/s, r[1] = us
- *           per round.
+ *           positions of its own slab of 2^p2 records (p2 in 10..18; 0 means
+ *           16, a 1 MiB slab) per round, p1 rounds (the edge record fetches
+ *           of the sending step); r[0] = G loads/s, r[1] = us per round.
  *   kind 3: p0 barriers among p1 (2..CUs) workgroups of a cooperative launch:
  *           r[0] = us per barrier of the cycle loop's kind; r[1] = us per
  *           fully fenced barrier after every member wrote p2 KiB with plain

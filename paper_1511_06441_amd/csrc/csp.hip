@@ -2886,10 +2886,10 @@ __global__ void __launch_bounds__(256) k_mb_atomic(unsigned *a, unsigned long lo
 
 // per workgroup and round, nr 16-byte loads at hashed positions of its own
 // slab of 65,536 records (1 MiB), four in flight per thread
-__global__ void __launch_bounds__(BLOCK) k_mb_loads(const uint4 *rec, int nr, int rounds, unsigned *sink)
+__global__ void __launch_bounds__(BLOCK) k_mb_loads(const uint4 *rec, int nr, int rounds, int lg, unsigned *sink)
 {
-    const unsigned tid = threadIdx.x, r = blockIdx.x;
-    const uint4 *my = rec + (size_t)r * 65536;
+    const unsigned tid = threadIdx.x, r = blockIdx.x, mask = (1u << lg) - 1u;
+    const uint4 *my = rec + ((size_t)r << lg);
     unsigned acc = 0;
     for (int it = 0; it < rounds; ++it) {
         for (int j0 = (int)tid; j0 < nr; j0 += BLOCK * 4) {
@@ -2897,7 +2897,7 @@ __global__ void __launch_bounds__(BLOCK) k_mb_loads(const uint4 *rec, int nr, in
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = j0 + u * BLOCK;
-                if (j < nr) v[u] = my[mb_hash((unsigned)(j * 977 + it * 131) + r) & 65535u];
+                if (j < nr) v[u] = my[mb_hash((unsigned)(j * 977 + it * 131) + r) & mask];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -4129,16 +4129,20 @@ int csp_microbench(csp_ctx *ctx, int kind, int64_t p0, int64_t p1, int64_t p2, d
         if (rc) return rc;
         r[0] = (double)p0 / (ms * 1e-3) / 1e9;
     } else if (kind == 2) {
-        // one workgroup per CU, p0 scattered 16-byte loads each per round, p1 rounds
-        if (p0 < 1 || p1 < 1) return fail(ctx, CSP_EINVAL, "load counts");
-        const size_t words = (size_t)ctx->num_cu * 65536 * 16 + 64;
+        // one workgroup per CU, p0 scattered 16-byte loads each per round
+        // in a slab of 2^p2 records, p1 rounds
+        const int lg = p2 == 0 ? 16 : (int)p2;
+        if (p0 < 1 || p1 < 1 || lg < 10 || lg > 18) return fail(ctx, CSP_EINVAL, "load counts or slab size");
+        const size_t slabs = (size_t)ctx->num_cu * ((size_t)16 << lg);
+        const size_t words = slabs + 64;
         rc = grow(ctx, &ctx->arena, ctx->arena_cap, words, "microbenchmark buffer");
         if (rc) return rc;
         HIP_TRY(hipMemsetAsync(ctx->arena, 1, words, s), "fill");
         const uint4 *rec = reinterpret_cast<const uint4 *>(ctx->arena);
-        unsigned *sink = reinterpret_cast<unsigned *>(ctx->arena + (size_t)ctx->num_cu * 65536 * 16);
+        unsigned *sink = reinterpret_cast<unsigned *>(ctx->arena + slabs);
         rc = timed([&] {
-            hipLaunchKernelGGL(k_mb_loads, dim3((unsigned)ctx->num_cu), dim3(BLOCK), 0, s, rec, (int)p0, (int)p1, sink);
+            hipLaunchKernelGGL(k_mb_loads, dim3((unsigned)ctx->num_cu), dim3(BLOCK), 0, s, rec, (int)p0, (int)p1, lg,
+                               sink);
         });
         if (rc) return rc;
         r[0] = (double)ctx->num_cu * (double)p0 * (double)p1 / (ms * 1e-3) / 1e9;
