@@ -1319,6 +1319,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     __shared__ unsigned s_ccnt[NOMAX];        // candidates shipped / received this cycle
     __shared__ unsigned s_nl, s_bhn;          // size of I_t; improved vertices of B
     __shared__ unsigned s_nbad;               // a neighbour never arrived (gang broken)
+    __shared__ unsigned s_sink;               // keeps the prefetch loads
     __shared__ unsigned s_cpre[NOMAX + 1];
 
     const unsigned tid = threadIdx.x, lane = lane_id();
@@ -1884,10 +1885,21 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         }
         par ^= 1u;
         PHASE4(2);
+        // While the release is on its way, bring the bucket of t + 1 (the
+        // usual next delivery time) into the L2: one word per 128-byte line,
+        // loaded by waves 1-15 (wave 0 waits for the release), consumed
+        // after it.
+        unsigned xb = 0;
+        {
+            const unsigned bk1 = (unsigned)((t + 1) & Wm);
+            const unsigned n1 = (unsigned)min((unsigned long long)cnt[bk1], S);
+            if (tid >= 64 && (tid - 64) * 16u < n1) xb = wheel[(unsigned long long)bk1 * S + (tid - 64) * 16u].x;
+        }
         if (!gang_or_wait(p.bar, G, r, epoch, p.wait_limit, mine, all) || s_nbad) {
             status = ST_BROKEN;
             break;
         }
+        if (xb == 0x9E3779B9u) *(volatile unsigned *)&s_sink = xb;
         PHASE4(4);
 
         // the counters' sums are needed by the lead only; it clears the
