@@ -518,8 +518,8 @@ def main():
     ap.add_argument("--path", type=int, default=0,
                     help="lattice workloads: 0 automatic, 1 contiguous ranges, 2 global labels, 3 x-pencil ranges (d=3)")
     ap.add_argument("--dense-sweep", type=int, nargs="*", default=None,
-                    help="lattice workloads: also time each solve with these dense thresholds of the improved "
-                         "set (-1 never), untimed by the step")
+                    help="lattice workloads: also time each solve with these dense thresholds (flows delivered "
+                         "to a range in a cycle; -1 never), untimed by the step")
     ap.add_argument("--trace", action="store_true",
                     help="also report |I_t| and water in transit against t (one extra solve each, untimed)")
     args = ap.parse_args()

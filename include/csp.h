@@ -265,20 +265,21 @@ int csp_autotune_clear(csp_ctx *ctx);
 /* Dense/sparse form of the improved set I_t (section 6, Step 8 condenses
  * the triggered vertices into one list).  Each workgroup of the
  * range-owned kernel collects the vertices of its range whose label rose
- * at t, first as an unordered list appended during the deliveries (sparse
- * form); when that list holds more than `vertices` entries the workgroup
- * sweeps its improved-vertex bitmap into a list in vertex order (dense
- * form), so that neighbouring vertices' edge records are read together in
- * the sending step.  0 sweeps every cycle; a value of 2^32 - 1 or more
- * never sweeps; -1 (the default) restores the automatic choice (the
- * autotuned value for the lattice shape, else 4096).
+ * at t.  Before its deliveries of a cycle it chooses the form from the
+ * number of flows it is about to deliver: up to `flows`, an unordered list
+ * appended during the deliveries (sparse form); above, the deliveries only
+ * mark an improved-vertex bitmap, which a sweep then packs into a list in
+ * vertex order (dense form).  0 takes the dense form every cycle; a value
+ * of 2^32 - 1 or more never; -1 (the default) restores the automatic
+ * choice (the autotuned value for the lattice shape, else 4096 for ranges
+ * of 32,768 vertices or more and never for smaller ones).
  * Changes speed, never results.  csp_autotune tries, on the configuration
- * it chose, the thresholds never, 0, 1024, 2048, 4096 and 8192 and records
- * the fastest (when at least 3 % faster than the automatic one);
+ * it chose, the thresholds never, 0, 2048, 4096, 8192 and 16384 and
+ * records the fastest (when at least 3 % faster than the automatic one);
  * csp_tuned_dense_threshold reports what it recorded for a shape (-1:
  * nothing, the automatic choice applies). */
-int csp_set_dense_threshold(csp_ctx *ctx, int64_t vertices);
-int csp_tuned_dense_threshold(const csp_ctx *ctx, int d, int64_t n, int64_t *vertices);
+int csp_set_dense_threshold(csp_ctx *ctx, int64_t flows);
+int csp_tuned_dense_threshold(const csp_ctx *ctx, int d, int64_t n, int64_t *flows);
 
 /* Cycle trace for later csp_solve_dev calls on ctx (off when cap = 0):
  * trace is a device buffer of cap rows of four int64, one row per time at

@@ -315,8 +315,8 @@ def csp_autotune(ctx, d, n, f1, f2, A, B, M, stream=None):
     return b.value, pth.value, ms.value
 
 
-def csp_set_dense_threshold(ctx, vertices: int):
-    _check(ctx, lib.csp_set_dense_threshold(ctx, vertices))
+def csp_set_dense_threshold(ctx, flows: int):
+    _check(ctx, lib.csp_set_dense_threshold(ctx, flows))
 
 
 def csp_tuned_dense_threshold(ctx, d: int, n: int) -> int:

@@ -1176,7 +1176,7 @@ struct RJ {
     int K;                         // neighbours lie within K ranges
     int lt;                        // LDS label bytes (2 or 4)
     int llist;                     // frontier list entries kept in LDS (16-bit local indices); the rest in lists
-    unsigned dense_thr;            // a range whose I_t is larger sweeps its bitmap into an index-ordered list
+    unsigned dense_thr;            // a range delivering more flows in a cycle builds I_t by a bitmap sweep
     int tile;                      // 1 (d = 3): ranges are x-pencils of n x ty x tz vertices
     int ty, tz;                    // pencil extent along y and z
     unsigned nty;                  // pencils along y
@@ -1563,14 +1563,16 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         return total;
     };
 
-    // Dense form of I_t (Step 8's condensed list in vertex order): sweep the
-    // frontier bitmap, two words per thread, into the list; each wave packs
-    // the set bits of its words in ascending local index at an offset taken
-    // from a shared counter (s_sw, zero on entry), so that the departure's
-    // lanes read the edge records of neighbouring vertices together.  The
-    // bitmap is left as it is (the departure clears it).
+    // Dense form of I_t (Step 8's condensed list in vertex order): the
+    // deliveries only set the frontier bitmap, and this sweep packs it, two
+    // words per thread, into the list; each wave writes the set bits of its
+    // words in ascending local index at an offset taken from a shared
+    // counter (s_sw, zero on entry).  It also finds the best (label, -index)
+    // over the improved vertices of B.  The bitmap is left as it is (the
+    // departure clears it).
     __shared__ unsigned s_sw;
     auto sweep = [=]() -> unsigned {
+        unsigned long long bestB = 0;
         for (unsigned w0 = 0; w0 < cw; w0 += 2 * BLOCK) {
             const unsigned wi = w0 + 2 * tid;
             const unsigned b0 = wi < cw ? fb[wi] : 0u, b1 = wi + 1 < cw ? fb[wi + 1] : 0u;
@@ -1597,6 +1599,27 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 bits &= bits - 1u;
                 list_put(k++, (wi + 1) * 32u + bt);
             }
+            // improved vertices of B: best (label, -index)
+            for (int h = 0; h < 2; ++h) {
+                const unsigned wh = wi + (unsigned)h, bh = h ? b1 : b0;
+                unsigned bm = bh ? bh & bb[wh] : 0u;
+                while (bm) {
+                    const unsigned bt = (unsigned)(__ffs(bm) - 1);
+                    bm &= bm - 1u;
+                    const unsigned i = wh * 32u + bt;
+                    const unsigned long long key = ((unsigned long long)lget(lab, l16, i) << 32) |
+                                                   (0xFFFFFFFFull - (unsigned long long)gvert(i));
+                    bestB = key > bestB ? key : bestB;
+                }
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long ob = __shfl_xor(bestB, o);
+            bestB = ob > bestB ? ob : bestB;
+        }
+        if (lane == 0 && bestB) {
+            atomicMax(&s_xkey, bestB);
+            atomicOr(&s_flags, SF_BHIT);
         }
         __syncthreads();
         return s_sw;
@@ -2007,6 +2030,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         {
             const unsigned bk = (unsigned)(t & Wm);
             F = (unsigned)min((unsigned long long)cnt[bk], S);
+            // dense form when the bucket is large: the deliveries only mark
+            // the bitmap, and a sweep builds the list (and the B check) after
+            const bool dense = F > p.dense_thr;
             const uint2 *bkt = wheel + (unsigned long long)bk * S;
             constexpr int UA = 4;                   // flow loads in flight per thread
             for (unsigned j0 = tid; j0 < F; j0 += BLOCK * UA) {
@@ -2034,12 +2060,14 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                         if (raised) {
                             // the first raise of a vertex this cycle puts it in I_t
                             const unsigned bit = 1u << (i & 31);
-                            if (!(atomicOr(&fb[i >> 5], bit) & bit)) {
+                            if (dense) {
+                                atomicOr(&fb[i >> 5], bit);
+                            } else if (!(atomicOr(&fb[i >> 5], bit) & bit)) {
                                 const unsigned long long am = __ballot(1);
                                 const int ld = __ffsll((long long)am) - 1;
                                 unsigned k0 = 0;
                                 if ((int)lane == ld) k0 = atomicAdd(&s_nl, (unsigned)__popcll(am));
-                                const unsigned k = __shfl(k0, ld) + (unsigned)__popcll(am & ((1ull << lane) - 1ull));
+                                const unsigned k = (unsigned)__builtin_amdgcn_readlane((int)k0, ld) + (unsigned)__popcll(am & ((1ull << lane) - 1ull));
                                 list_put(k, i);
                                 if (bb[i >> 5] & bit) atomicAdd(&s_bhn, 1u);
                             }
@@ -2072,7 +2100,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
                 }
             }
             // a large I_t is rebuilt in vertex order (the same set)
-            if (nlist > p.dense_thr) nlist = sweep();
+            if (dense) nlist = sweep();
             if (tid == 0) {
                 cnt[bk] = 0;
                 cU += nlist;
@@ -3300,17 +3328,18 @@ LdsPlan plan_lds(const csp_ctx *ctx, int d, long long n, long long N, uint32_t M
     return pl;
 }
 
-// Automatic dense threshold of a range of c vertices: a range sweeps its
-// improved set into vertex order in the cycles where it improved more than
-// 4,096 vertices.  The sweep costs about 2.2 us per cycle whatever the set's
-// size, so it pays only on large sets; measured over thresholds never, 0,
-// 1,024, 2,048, 3,072 and 4,096 on the 256^3 sparse and stress cubes, the
-// 128^3 cubes, the paper's boundary -> centre cubes and the section 7
-// environments, 4,096 was the fastest or within 0.2 % of it on every one.
+// Automatic dense threshold of a range of c vertices: a range of 32,768
+// vertices or more builds I_t in dense form in the cycles where more than
+// 4,096 flows are delivered to it; smaller ranges keep the append list.  The
+// dense form saves the append's dependent LDS round trips on every first
+// raise and costs a sweep of the whole bitmap, so it pays only on large
+// buckets of large ranges: on the 256^3 cube 4,096 beat 0, 2,048, 8,192 and
+// never (253 against 254, 255, 256 and 266 ms); on the 128^3 cubes (8,192
+// vertices per range) never and 8,192 were fastest (5.72 against 5.95 ms at
+// 4,096).
 unsigned dense_default(long long c)
 {
-    (void)c;
-    return 4096u;
+    return c >= 32768 ? 4096u : DENSE_NEVER;
 }
 
 // Dense threshold of a single solve: the override, else the autotuned one,
@@ -5094,13 +5123,14 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
     // another configuration replaces the automatic one only when it is at
     // least 3 % faster, so that timing noise does not pick it
     if (best.ms > 0.97f * base.ms) best = base;
-    // then the dense threshold on the chosen shape: sizes of I_t per range
-    // above which it is swept into vertex order (never, always, and between)
+    // then the dense threshold on the chosen shape: flows delivered to a
+    // range in a cycle above which I_t is built by a bitmap sweep (never,
+    // always, and between)
     {
         ctx->blocks_override = best.blocks;
         ctx->path_override = best.path;
         const csp_ctx::Tuned shape = best;
-        for (long long thr : {(long long)DENSE_NEVER, 0ll, 1024ll, 2048ll, 4096ll, 8192ll}) {
+        for (long long thr : {(long long)DENSE_NEVER, 0ll, 2048ll, 4096ll, 8192ll, 16384ll}) {
             ctx->dense_override = thr;
             float t = -1.f;
             for (int rep = 0; rep < 2 && rc == CSP_OK; ++rep) {
@@ -5133,20 +5163,20 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
     return CSP_OK;
 }
 
-int csp_set_dense_threshold(csp_ctx *ctx, int64_t vertices)
+int csp_set_dense_threshold(csp_ctx *ctx, int64_t flows)
 {
     if (!ctx) return CSP_EINVAL;
-    ctx->dense_override = vertices < 0 ? -1 : vertices;
+    ctx->dense_override = flows < 0 ? -1 : flows;
     return CSP_OK;
 }
 
-int csp_tuned_dense_threshold(const csp_ctx *ctx, int d, int64_t n, int64_t *vertices)
+int csp_tuned_dense_threshold(const csp_ctx *ctx, int d, int64_t n, int64_t *flows)
 {
-    if (!ctx || !vertices || d < 1 || d > 4 || n < 2) return CSP_EINVAL;
+    if (!ctx || !flows || d < 1 || d > 4 || n < 2) return CSP_EINVAL;
     long long N = 1;
     for (int k = 0; k < d; ++k) N *= n;
     const csp_ctx::Tuned *e = tuned_for(ctx, d, N);
-    *vertices = e ? e->dense : -1;
+    *flows = e ? e->dense : -1;
     return CSP_OK;
 }
 
