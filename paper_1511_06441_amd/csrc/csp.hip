@@ -1021,10 +1021,8 @@ __device__ __forceinline__ void gang_or_sums(BarHdr *bh, unsigned g, unsigned e,
 }
 
 // First half of gang_or: member m arrives at barrier epoch + 1 (epoch is
-// advanced).  Before its arrival it stores the new epoch in word 12 of its
-// slot line, after every access of the workgroup has completed: a range
-// that reads this member's candidates may do so once it sees that word,
-// without waiting for the whole gang.  The member that completes the root
+// advanced) once every access of the workgroup has completed; waves 1 and
+// up return at once, wave 0 arrives.  The member that completes the root
 // releases everyone here.
 __device__ void gang_or_arrive(BarHdr *bh, unsigned g, unsigned m, unsigned &epoch, const Comb &mine,
                                unsigned long long *tpub = nullptr)
@@ -1046,7 +1044,6 @@ __device__ void gang_or_arrive(BarHdr *bh, unsigned g, unsigned m, unsigned &epo
     if (tpub && lane == 0) *tpub = wall_clock64();
     unsigned long long comb = 0, rel = 2;  // rel: 2 not the releaser, 1 releaser reading far deltas, 0 releaser
     if (lane == 0) {
-        st64(&bar_slot(bh, m)[12], (unsigned long long)e);
         unsigned long long w = (1ull << (m - grp * MG)) | ((unsigned long long)(mine.orf >> 28) << 32);
         if (mine.mn != 0xFFFFFFFFu) w |= mine.mn <= OR_ND ? 1ull << (OR_D0 + mine.mn - 1) : 1ull << OR_FAR;
         unsigned long long *gw = &bh->ow[e & 1][grp][0];
@@ -1087,25 +1084,6 @@ __device__ void gang_or_arrive(BarHdr *bh, unsigned g, unsigned m, unsigned &epo
         }
         const unsigned long long rw = tag | ((unsigned long long)orf4 << 16) | (mn < 0xFFFFu ? mn : 0xFFFFu);
         for (unsigned i = lane; i < g; i += 64) st64(&bar_flag(bh, g, i)[0], rw);
-    }
-}
-
-// Wait until member m of a gang whose members announce their arrival with
-// gang_or_arrive has arrived at barrier e (word 12 of its slot line); false
-// after `limit` ticks or when the gang is broken.  One lane calls it.
-__device__ bool gang_or_seen(BarHdr *bh, unsigned m, unsigned e, unsigned long long limit)
-{
-    const unsigned long long *w = &bar_slot(bh, m)[12];
-    if (ld64(w) >= (unsigned long long)e) return true;
-    const unsigned long long t0 = wall_clock64();
-    for (;;) {
-        __builtin_amdgcn_s_sleep(1);
-        if (ld64(w) >= (unsigned long long)e) return true;
-        if (wall_clock64() - t0 > limit) {
-            __hip_atomic_store(&bh->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        if (__hip_atomic_load(&bh->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
     }
 }
 
@@ -1190,7 +1168,7 @@ struct RJ {
     uint2 *pool;                   // [g][W][S] wheel of each range
     unsigned long long pool_flows;
     uint2 *cand;                   // [2][g][NO][cand_cap] candidates by sender and offset
-    unsigned *pubc;                // [2][g][NOMAX] candidate fills
+    unsigned long long *pubc;      // [2][g][NOMAX] candidate fills, tagged with the barrier epoch
     BarHdr *bar;
     Out *out;
     unsigned *labels_out;
@@ -1385,7 +1363,7 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
     };
     auto list_get = [=](unsigned k) -> unsigned { return k < lcap ? (unsigned)lds_list[k] : mylist[k]; };
     uint2 *const cand = p.cand;
-    unsigned *const pubc_base = p.pubc;
+    unsigned long long *const pubc_base = p.pubc;
     const unsigned long long ccap = p.cand_cap;
     auto candbuf = [=](unsigned par, unsigned long long src, unsigned oi) {
         return cand + (((unsigned long long)par * G + src) * NO + oi) * ccap;
@@ -1803,12 +1781,9 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         for (int o = 32; o > 0; o >>= 1) amin = min(amin, (unsigned)__shfl_xor(amin, o));
         if (lane == 0 && amin != 0xFFFFFFFFu) atomicMin(&s_min, amin);
         __syncthreads();
-        // publish candidate fills; next delivery time seen from this range
-        if (tid < (unsigned)NO && soff((int)tid) != 0) {
-            const unsigned v = s_ccnt[tid];
-            if (v > CS) atomicOr(&s_flags, SF_OVER);
-            __hip_atomic_store(pubc(par, r, tid), min(v, CS), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        // candidate fills (published after the barrier arrival); next
+        // delivery time seen from this range
+        if (tid < (unsigned)NO && soff((int)tid) != 0 && s_ccnt[tid] > CS) atomicOr(&s_flags, SF_OVER);
         {
             unsigned best = 0xFFFFFFFFu, over = 0;
             for (unsigned bk = tid; bk < W; bk += BLOCK) {
@@ -1842,22 +1817,39 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         PHASE4(1);
         // ---- Steps 4-5 across ranges: test the candidates the neighbours
         // shipped at t against this range's labels (still L_t) and file the
-        // flows, while the barrier completes: a neighbour's candidates are
-        // complete once it has arrived.  A run that ends at this barrier
-        // (T found, overflow) discards what is filed here; it is counted
-        // (cEx) only when the run goes on.
+        // flows, while the barrier completes.  Every access of the departure
+        // has completed (gang_or_arrive waited for them), so each fill count
+        // is published now, tagged with the barrier's epoch; a neighbour's
+        // candidates are complete once its count with this epoch is seen.  A
+        // run that ends at this barrier (T found, overflow) discards what is
+        // filed here; it is counted (cEx) only when the run goes on.
         unsigned long long cEx = 0;
         if (tid >= 64 && tid - 64 < (unsigned)NO) {      // wave 1: wave 0 is arriving
             const unsigned sl = tid - 64;
             const long long so = soff((int)sl);           // slot sl comes from range r - so
+            if (so != 0)
+                st64(pubc(par, r, sl), ((unsigned long long)epoch << 32) | min(s_ccnt[sl], CS));
             const long long src = (long long)r - so;
             unsigned v = 0;
             if (so != 0 && src >= 0 && src < (long long)G) {
-                if (gang_or_seen(p.bar, (unsigned)src, epoch, p.wait_limit))
-                    v = __hip_atomic_load(pubc(par, (unsigned long long)src, sl), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                else
-                    s_nbad = 1;
+                const unsigned long long *w = pubc(par, (unsigned long long)src, sl);
+                unsigned long long x = ld64(w);
+                if ((x >> 32) < (unsigned long long)epoch) {
+                    const unsigned long long t0 = wall_clock64();
+                    for (;;) {
+                        __builtin_amdgcn_s_sleep(1);
+                        x = ld64(w);
+                        if ((x >> 32) >= (unsigned long long)epoch) break;
+                        if (wall_clock64() - t0 > p.wait_limit ||
+                            __hip_atomic_load(&p.bar->broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            __hip_atomic_store(&p.bar->broken, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            s_nbad = 1;
+                            x = 0;
+                            break;
+                        }
+                    }
+                }
+                v = (unsigned)x;
             }
             s_ccnt[sl] = v;
         }
@@ -3084,7 +3076,7 @@ struct csp_ctx {
     long long last_trace_rows = 0;
     int last_path = 0;
     size_t lds_limit = 65536;
-    unsigned *pub = nullptr;        // candidate fills [2][G][NOMAX]
+    unsigned long long *pub = nullptr;   // candidate fills [2][G][NOMAX]
     size_t pub_cap = 0;
     uint2 *cand = nullptr;          // candidates [2][G][NO][cap]
     size_t cand_cap = 0;
@@ -3793,7 +3785,7 @@ int solve_noalloc(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
                   : std::min<unsigned long long>(cand_max, std::max<unsigned long long>(4096ull, plan.c / 2));
     const size_t off_lists = up((size_t)(plan.c * G) * rec_bytes(d));
     const size_t off_pub = off_lists + up((size_t)(plan.c * G) * 4);
-    const size_t off_cand = off_pub + up((size_t)2 * G * NOMAX * 4);
+    const size_t off_cand = off_pub + up((size_t)2 * G * NOMAX * 8);
     const size_t off_pool = off_cand + up((size_t)(2ull * G * NO * ccap * 8));
     // the wheel gets the rest; at least 16 flows per bucket of every range
     if (off_pool + (size_t)G * MAXW * 16 * 8 > (size_t)CSP_SCRATCH_BYTES)
@@ -3806,7 +3798,7 @@ int solve_noalloc(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     p.dense_thr = dense_for(ctx, d, N, plan.c);
     p.rec = ctx->scratch;
     p.lists = reinterpret_cast<unsigned *>(ctx->scratch + off_lists);
-    p.pubc = reinterpret_cast<unsigned *>(ctx->scratch + off_pub);
+    p.pubc = reinterpret_cast<unsigned long long *>(ctx->scratch + off_pub);
     p.cand = reinterpret_cast<uint2 *>(ctx->scratch + off_cand);
     p.cand_cap = (unsigned)ccap;
     p.pool = reinterpret_cast<uint2 *>(ctx->scratch + off_pool);
@@ -4332,7 +4324,7 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
             pl.off_cand = at;
             at = up(at + (size_t)(2ull * pl.g * NO * pl.ccap * 8));
             pl.off_pubc = at;
-            at = up(at + (size_t)2 * pl.g * NOMAX * 4);
+            at = up(at + (size_t)2 * pl.g * NOMAX * 8);
             pl.off_bar = at;
             at = up(at + bar_bytes((unsigned)pl.g));
             pl.off_out = at;
@@ -4387,7 +4379,7 @@ int csp_solve_batch(csp_ctx *ctx, int count, const csp_problem *probs, csp_resul
             p.pool_flows = pl.pool;
             p.cand = reinterpret_cast<uint2 *>(ctx->arena + pl.off_cand);
             p.cand_cap = (unsigned)pl.ccap;
-            p.pubc = reinterpret_cast<unsigned *>(ctx->arena + pl.off_pubc);
+            p.pubc = reinterpret_cast<unsigned long long *>(ctx->arena + pl.off_pubc);
             p.bar = reinterpret_cast<BarHdr *>(ctx->arena + pl.off_bar);
             p.out = reinterpret_cast<Out *>(ctx->arena + pl.off_out);
             p.labels_out = q.labels;
@@ -4619,7 +4611,7 @@ size_t srv_footprint(const SrvReq &r)
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t NO = 2 * pl.K + 1;
     return up((size_t)pl.N * rec_bytes(r.q.d)) + up((size_t)pl.g * pl.c * 4) + up((size_t)pl.pool * 8) +
-           up(2ull * pl.g * NO * pl.ccap * 8) + up((size_t)2 * pl.g * NOMAX * 4) +
+           up(2ull * pl.g * NO * pl.ccap * 8) + up((size_t)2 * pl.g * NOMAX * 8) +
            up((size_t)pl.g * ((pl.c + 31) / 32) * 4);
 }
 
@@ -4707,8 +4699,8 @@ int srv_admit(csp_server *s)
         w.rj.cand = reinterpret_cast<uint2 *>(s->arena + at);
         w.rj.cand_cap = (unsigned)pl.ccap;
         at += up(2ull * pl.g * (2 * pl.K + 1) * pl.ccap * 8);
-        w.rj.pubc = reinterpret_cast<unsigned *>(s->arena + at);
-        at += up((size_t)2 * pl.g * NOMAX * 4);
+        w.rj.pubc = reinterpret_cast<unsigned long long *>(s->arena + at);
+        at += up((size_t)2 * pl.g * NOMAX * 8);
         w.abits = reinterpret_cast<unsigned *>(s->arena + at);
         w.rj.bar = reinterpret_cast<BarHdr *>(s->fixed + s->off_bar + (size_t)j * s->bar_stride);
         w.rj.out = nullptr;
