@@ -125,7 +125,7 @@ def run_batch(args):
         "roofline": {"bound": "hbm", "kernel": "k_batch<2>, k_batch<3>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel_ms_avg": kms, "algorithmic_bytes_per_step": bytes_step},
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_batch(),
     }
     if tuned:
         line["autotune"] = tuned
@@ -467,6 +467,37 @@ def _oracle_window(args):
 def _gen():
     from paper_1511_06441_amd import inputs as gen
     return gen
+
+
+def _oracle_mixed(j):
+    """Oracle solve of problem j of the 1,024-problem batch: (R, seconds)."""
+    inst = _gen().mixed_instance(41, j)
+    return _oracle_run(inst, 0)
+
+
+def cpu_baseline_batch(step=64):
+    """The oracle on every step-th problem of the batch, instance-parallel over
+    the host's processes (at most 16), each process timing its own solves."""
+    import multiprocessing as mp
+    gen = _gen()
+    nproc = len(os.sched_getaffinity(0))
+    procs = max(1, min(16, nproc))
+    js = list(range(0, 1024, step))
+    verts = sum(n ** d for (_, d, n, _, _) in (gen.mixed_params(41, j) for j in js))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        runs = pool.map(_oracle_mixed, js, chunksize=1)
+    wall = time.perf_counter() - t0
+    R = sum(r for r, _ in runs)
+    cpu_s = sum(t for _, t in runs)
+    return dict(value=R / cpu_s, unit="relaxations/s", cores=1, kind="oracle",
+                sample=(f"problems 0, {step}, ..., {js[-1]} of the batch ({len(js)} problems, {verts:,} vertices), "
+                        f"single-threaded C oracle (-O2): R={R} in {cpu_s:.1f} s of solve time"),
+                seconds=round(cpu_s, 2), cpu_model=_cpu_model(), nproc=nproc,
+                solves_per_s=len(js) / cpu_s,
+                parallel={"value": R / wall, "processes": procs, "solves_per_s": len(js) / wall,
+                          "seconds": round(wall, 2),
+                          "how": "instance-parallel: the sample's problems spread over a pool of processes"})
 
 
 def cpu_baseline(workload, inst):

@@ -63,3 +63,15 @@ def test_cpu_window_sample_is_bounded():
     whole solve."""
     k1, k2 = bench.WORKLOADS["cube256"]["sample_cycles"]
     assert 0 < k1 < k2 <= 2000
+
+
+def test_batch_cpu_sample_is_bounded():
+    """The batch's CPU sample is every 64th problem (16 of 1,024), a few
+    million vertices in all, and the default bench line takes it."""
+    import inspect
+    from paper_1511_06441_amd import inputs as gen
+    step = inspect.signature(bench.cpu_baseline_batch).parameters["step"].default
+    js = range(0, 1024, step)
+    assert len(js) == 16
+    verts = sum(n ** d for (_, d, n, _, _) in (gen.mixed_params(41, j) for j in js))
+    assert verts < 6_000_000
