@@ -262,6 +262,17 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
                  const uint8_t *B, uint32_t M, int *blocks, int *path, float *ms, void *stream);
 int csp_autotune_clear(csp_ctx *ctx);
 
+/* Limit on every barrier and neighbour wait of the single-solve entry points
+ * (csp_solve, csp_solve_dev, csp_solve_dev_noalloc, csp_solve_graph_dev, the
+ * reconstructions and csp_autotune) for later calls on ctx, in
+ * microseconds: a wait longer than this marks the run broken, every
+ * workgroup leaves the kernel, and the call fails with CSP_EDEVICE.  -1
+ * restores the default (20 s).  A limit far below a cycle's length makes
+ * every solve with more than one workgroup fail; it exists so that the
+ * failure path can be exercised.  Batches and the server keep their own
+ * limit (60 s). */
+int csp_set_wait_limit(csp_ctx *ctx, int64_t microseconds);
+
 /* Dense/sparse form of the improved set I_t (section 6, Step 8 condenses
  * the triggered vertices into one list).  Each workgroup of the
  * range-owned kernel collects the vertices of its range whose label rose

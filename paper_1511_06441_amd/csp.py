@@ -31,7 +31,7 @@ EXPORTED = (
     "csp_serve_poll", "csp_serve_pending", "csp_serve_close", "csp_set_trace", "csp_last_trace_rows",
     "csp_reconstruct_log_dev", "csp_solve_graph_dev", "csp_autotune", "csp_autotune_clear",
     "csp_set_batch_target", "csp_autotune_batch", "csp_reconstruct",
-    "csp_set_dense_threshold", "csp_tuned_dense_threshold", "csp_last_phase_spread",
+    "csp_set_dense_threshold", "csp_tuned_dense_threshold", "csp_last_phase_spread", "csp_set_wait_limit",
     "csp_solve_dev_noalloc", "csp_microbench",
 )
 
@@ -133,6 +133,8 @@ def _load():
     lib.csp_last_trace_rows.restype = i32
     lib.csp_last_phase_spread.argtypes = [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.csp_last_phase_spread.restype = i32
+    lib.csp_set_wait_limit.argtypes = [p, i64]
+    lib.csp_set_wait_limit.restype = i32
     lib.csp_set_dense_threshold.argtypes = [p, i64]
     lib.csp_set_dense_threshold.restype = i32
     lib.csp_tuned_dense_threshold.argtypes = [p, i32, i64, ctypes.POINTER(i64)]
@@ -313,6 +315,11 @@ def csp_autotune(ctx, d, n, f1, f2, A, B, M, stream=None):
     _check(ctx, lib.csp_autotune(ctx, d, n, _ptr(f1), _ptr(f2), _ptr(A), _ptr(B), M, ctypes.byref(b),
                                  ctypes.byref(pth), ctypes.byref(ms), _stream(stream)))
     return b.value, pth.value, ms.value
+
+
+def csp_set_wait_limit(ctx, microseconds: int):
+    """Barrier wait limit of later single solves (-1: the default, 20 s)."""
+    _check(ctx, lib.csp_set_wait_limit(ctx, microseconds))
 
 
 def csp_set_dense_threshold(ctx, flows: int):

@@ -1907,7 +1907,8 @@ __device__ RunRes range_run(const RJ &p, unsigned r, unsigned *smem, unsigned M,
         unsigned xb = 0;
         {
             const unsigned bk1 = (unsigned)((t + 1) & Wm);
-            const unsigned n1 = (unsigned)min((unsigned long long)cnt[bk1], S);
+            const unsigned c1 = __hip_atomic_load(&cnt[bk1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const unsigned n1 = (unsigned)min((unsigned long long)c1, S);
             if (tid >= 64 && (tid - 64) * 16u < n1) xb = wheel[(unsigned long long)bk1 * S + (tid - 64) * 16u].x;
         }
         if (!gang_or_wait(p.bar, G, r, epoch, p.wait_limit, mine, all) || s_nbad) {
@@ -3063,6 +3064,7 @@ struct csp_ctx {
         long long dense;            // dense threshold (-1: automatic)
     };
     long long dense_override = -1;  // -1 automatic, else the threshold for later solves
+    long long wait_us = -1;         // -1 default (20 s), else the barrier wait limit of later solves
     std::vector<Tuned> tuned;
     long long batch_target = 0;     // batch: vertices per workgroup (0 = fewest workgroups)
     // batch: wheel pool and candidate capacity a problem (same lattice, masks
@@ -3229,7 +3231,6 @@ const csp_ctx::Tuned *tuned_for(const csp_ctx *ctx, int d, long long N)
     return nullptr;
 }
 
-// Kernel choice of a solve: the override, else the autotuned one, else automatic.
 // Kernel path of a solve: the override, else the autotuned one, else
 // x-pencil ranges for 3-d lattices of 2^23 vertices or more and the
 // automatic choice below that.  Pencils ship candidates only across their
@@ -3345,6 +3346,14 @@ unsigned dense_for(const csp_ctx *ctx, int d, long long N, long long c)
     }
     if (v < 0) return dense_default(c);
     return v >= (long long)DENSE_NEVER ? DENSE_NEVER : (unsigned)v;
+}
+
+// Wall-clock ticks a barrier wait of a single solve may take before the run
+// is marked broken: 20 s, or what csp_set_wait_limit set.
+unsigned long long solve_wait_ticks(const csp_ctx *ctx)
+{
+    if (ctx->wait_us < 0) return ctx->wall_khz * 1000ull * 20ull;
+    return ctx->wall_khz * (unsigned long long)ctx->wait_us / 1000ull;
 }
 
 void fill_job(RJ &p, int d, long long n, long long N, const LdsPlan &plan, const uint8_t *f1, const uint8_t *f2, const uint8_t *A, const uint8_t *B, uint32_t M)
@@ -3629,7 +3638,7 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
             p.out = &ctx->ctl->rout;
             p.labels_out = labels;
             p.max_cycles = max_cycles;
-            p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+            p.wait_limit = solve_wait_ticks(ctx);
             p.prof = ctx->prof;
             p.trace = ctx->trace;
             p.trace_cap = ctx->trace_cap;
@@ -3668,7 +3677,7 @@ int solve_impl(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_t 
             p.ctl = ctx->ctl;
             p.labels_out = labels;
             p.max_cycles = max_cycles;
-            p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+            p.wait_limit = solve_wait_ticks(ctx);
             p.prof = ctx->prof;
             void *args[] = {&p};
             HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
@@ -3807,7 +3816,7 @@ int solve_noalloc(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8
     p.out = &ctx->ctl->rout;
     p.labels_out = labels;
     p.max_cycles = max_cycles;
-    p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+    p.wait_limit = solve_wait_ticks(ctx);
     p.prof = ctx->prof;
     void *args[] = {&p};
     HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
@@ -3929,7 +3938,7 @@ int csp_solve_graph_dev(csp_ctx *ctx, int64_t nv, const int64_t *off, const int3
         p.xsel = &ctx->ctl->xkey;
         p.labels_out = labels;
         p.max_cycles = max_cycles;
-        p.wait_limit = ctx->wall_khz * 1000ull * 20ull;   // 20 s
+        p.wait_limit = solve_wait_ticks(ctx);
         p.prof = ctx->prof;
         void *args[] = {&p};
         HIP_TRY(hipEventRecord(ctx->ev0, s), "event");
@@ -5152,6 +5161,13 @@ int csp_autotune(csp_ctx *ctx, int d, int64_t n, const uint8_t *f1, const uint8_
     if (blocks) *blocks = best.blocks;
     if (path) *path = best.path;
     if (ms) *ms = best.ms;
+    return CSP_OK;
+}
+
+int csp_set_wait_limit(csp_ctx *ctx, int64_t microseconds)
+{
+    if (!ctx) return CSP_EINVAL;
+    ctx->wait_us = microseconds < 0 ? -1 : microseconds;
     return CSP_OK;
 }
 
