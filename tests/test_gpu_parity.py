@@ -416,6 +416,34 @@ def test_reconstruct_log_vs_oracle(solver, torch, case, blocks, path):
     assert got.tolist() == path_ref.tolist()
 
 
+@pytest.mark.parametrize("case", [LOG_CASES[1], LOG_CASES[3], LOG_CASES[5]])
+@pytest.mark.parametrize("path", [1, 3])
+def test_reconstruct_log_dense_form_vs_oracle(solver, torch, case, path):
+    """The logged walk with I_t built in dense form every cycle (the bitmap
+    sweep orders the improved vertices, and so the log, differently) gives the
+    oracle's repeated-solve path, result and counters."""
+    from oracle import oracle as O
+    from paper_1511_06441_amd import csp
+    d, n, seed, K1, K2, M = case
+    inst = gen.opposite_faces(d, n, seed, K1, K2, M)
+    _say("case", inst.name, "blocks 16, path", path, "dense 0")
+    path_ref, res_ref, _ = O.reconstruct(d, n, inst.f1, inst.f2, inst.A, inst.B, M)
+    ref = _oracle(inst)
+    di = csp.to_device(inst)
+    csp.csp_set_blocks(solver.ctx, 16)
+    csp.csp_set_path(solver.ctx, path)
+    csp.csp_set_dense_threshold(solver.ctx, 0)
+    try:
+        got, res, cnt = solver.reconstruct_log(di)
+    finally:
+        csp.csp_set_blocks(solver.ctx, 0)
+        csp.csp_set_path(solver.ctx, 0)
+        csp.csp_set_dense_threshold(solver.ctx, -1)
+    assert res.tuple() == res_ref.tuple() == ref.tuple()
+    assert cnt.asdict() == ref.counters
+    assert got.tolist() == path_ref.tolist()
+
+
 @pytest.mark.parametrize("which", ["cube128", "paper75"])
 def test_reconstruct_log_equals_repeated_solves_full_size(solver, torch, which):
     from paper_1511_06441_amd import csp
